@@ -1,0 +1,34 @@
+"""FP64 CPU oracle for the per-frame keyframe depth update (DeepFusion, Sec. II).
+
+TEST INFRASTRUCTURE ONLY. Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import or run anything in this package.
+The GPU library never calls it, and this package imports nothing from the GPU
+library; the only code both sides share is the seeded input generator
+``kfsynth``, which holds none of the method's arithmetic.
+
+The oracle is written for a reader holding the paper, in the paper's order:
+
+* ``geometry``  - relative pose, projection pi(K T_C1W T_WC0 rho(x, d)) of the
+  photometric error (Sec. II-B), epipolar constants.
+* ``stereo``    - texture gate, epipolar search over equally spaced samples with
+  a five-point (or 5x5) SSD, interpolation between two steps, the finite
+  difference Jacobian and the variance (J^T J)^-1 of eq. (semi), the
+  inverse-depth filter and the conversion to log space (Sec. II-B).
+* ``fusion``    - the cost c(d, s) = c_semi + c_net + c_grad with Huber on every
+  term (Sec. II-C), its normal equations on the 5-point grid, a direct sparse
+  solve, Jacobi-preconditioned CG, and Gauss-Newton alternating between depth
+  and scale; plus a converged mode giving the unique minimiser.
+* ``pipeline``  - keyframe state: set prior, fuse frame, read depth.
+
+Every reading taken where the paper is silent or ambiguous is listed in
+``readings.READINGS`` and repeated in the design notes.
+
+Pins: every function here is checked by ``tests/test_oracle_*.py`` against
+closed forms, invariants, brute force or independent library routines; no
+function is "parity unpinned" except where a test's docstring says so.
+"""
+
+from . import geometry, stereo, fusion, pipeline, readings  # noqa: F401
+from .stereo import StereoParams  # noqa: F401
+from .fusion import SolverParams, PriorMaps, SemiMeasurements  # noqa: F401
+from .pipeline import OracleKeyframe  # noqa: F401
