@@ -1,0 +1,173 @@
+/*
+ * kf.h - C ABI of the keyframe depth-update library (gfx950 / MI355X).
+ *
+ * The library keeps one keyframe's depth state resident in device memory and
+ * updates it with every new frame, as in DeepFusion (Laidlow, Czarnowski,
+ * Leutenegger, arxiv 2207.12244):
+ *   - semi-dense estimation (Sec. II-B): per textured keyframe pixel, an SSD
+ *     search along the epipolar line of the new frame, interpolation between
+ *     two steps, the variance (J^T J)^-1 of eq. (semi), and an inverse-depth
+ *     Gaussian filter;
+ *   - optimisation (Sec. II-C): the cost c(d, s) = c_semi + c_net + c_grad with
+ *     Huber on every term, minimised by Gauss-Newton iterations that alternate
+ *     between the log-depth map and the scale, the depth step solved with
+ *     Jacobi-preconditioned conjugate gradients on the grid's 5-point system.
+ *
+ * Conventions
+ *   - Images and maps are H x W, row-major, pixel i = v * W + u; integer pixel
+ *     coordinates are pixel centres; depth is z-depth.
+ *   - Device pointers are hipMalloc'd (or torch) memory on the context's
+ *     device. Host pointers are marked "host".
+ *   - Poses are host double[16], row-major 4x4 camera-to-world SE(3) matrices
+ *     T_WC; they are copied at call time.
+ *   - Map element type follows cfg.precision: KF_F64 -> double, otherwise
+ *     float. Images are always uint8 grey levels.
+ *   - Every call except kf_read_depth, kf_read_stats, kf_export_state and
+ *     kf_import_state only enqueues work on cfg.stream and returns; those four
+ *     synchronise the stream before returning.
+ *   - Ownership: the caller owns the workspace and every buffer passed in.
+ *     kf_set_prior copies the image and priors into the workspace (they may be
+ *     freed once the stream has passed the call); image1 of kf_fuse_frame must
+ *     stay alive until the stream has passed that call.
+ *   - Errors: a call returns KF_OK or a negative kf_status and never throws.
+ *     Argument and state errors are detected on the host before any device
+ *     work is enqueued. Input errors found on the device (non-finite values,
+ *     variances <= 0) and a solver synchronisation timeout raise a device flag
+ *     that the next synchronising call returns (KF_ERR_INPUT, KF_ERR_TIMEOUT).
+ *     kf_last_error gives a message for the last failure on the context.
+ *   - Threading: a context is externally synchronised; distinct contexts are
+ *     independent (each has its own workspace).
+ */
+#ifndef KF_H
+#define KF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct kf_ctx kf_ctx;
+
+typedef enum {
+  KF_OK = 0,
+  KF_ERR_ARG = -1,      /* invalid argument or configuration */
+  KF_ERR_OOM = -2,      /* workspace too small */
+  KF_ERR_HIP = -3,      /* a HIP runtime call failed (message in kf_last_error) */
+  KF_ERR_STATE = -4,    /* call out of order (e.g. kf_fuse_frame before kf_set_prior) */
+  KF_ERR_INPUT = -5,    /* device found a non-finite input or a variance <= 0 */
+  KF_ERR_TIMEOUT = -6   /* a solver workgroup waited too long for its team (never expected) */
+} kf_status;
+
+/* Storage / arithmetic form. */
+typedef enum {
+  KF_F64 = 0,       /* double maps, double arithmetic, double images */
+  KF_F32 = 1,       /* float maps and arithmetic, float images */
+  KF_BF16_F32 = 2   /* float maps and arithmetic; keyframe image and patch buffers bf16 */
+} kf_precision;
+
+/* Matching pattern of the epipolar search (Sec. II-B). */
+typedef enum {
+  KF_PAT_LINE5 = 0, /* five points, 1 px apart, along the epipolar lines of both images */
+  KF_PAT_SQ5X5 = 1  /* 5x5 square patch, translation-only warp */
+} kf_pattern;
+
+typedef struct {
+  int32_t width, height;        /* keyframe size; 8 <= width, height <= 8192 */
+  double fx, fy, cx, cy;        /* pinhole intrinsics K */
+  int32_t n_samples;            /* epipolar samples per pixel: a power of two in [4, 1024] */
+  int32_t pattern;              /* kf_pattern */
+  int32_t n_gn;                 /* Gauss-Newton iterations per frame (paper: 10), >= 1 */
+  int32_t n_cg;                 /* PCG iterations per GN iteration when cg_rtol == 0, >= 1 */
+  double cg_rtol;               /* > 0: PCG until ||r|| <= cg_rtol ||b||, at most cg_max */
+  int32_t cg_max;               /* cap of the tolerance mode, >= 1 */
+  double huber_delta;           /* Huber threshold on whitened residuals (> 0, may be INFINITY) */
+  double d_near, d_far;         /* depth range of a full-line search, 0 < d_near < d_far */
+  double grad_gate;             /* texture gate: |grad I0| >= grad_gate grey levels per pixel */
+  double sigma_photo;           /* photometric noise (grey levels) in eq. (semi), > 0 */
+  double r_floor;               /* floor of the log-space semi-dense variance, > 0 */
+  int32_t precision;            /* kf_precision */
+  int32_t solver_tiles_x;       /* solver workgroup grid (0, 0 = automatic) */
+  int32_t solver_tiles_y;
+  void* stream;                 /* hipStream_t the context enqueues on (NULL = null stream) */
+  void* workspace;              /* device buffer of at least kf_workspace_bytes(cfg) bytes */
+  size_t workspace_bytes;
+} kf_config;
+
+/* Per-frame statistics, valid after kf_read_stats. */
+typedef struct {
+  int32_t n_searched;       /* textured pixels searched by the last stereo update */
+  int32_t n_updated;        /* of which produced a measurement ("inliers", Sec. II) */
+  int32_t n_valid;          /* pixels with a semi-dense estimate after the last solve */
+  int32_t cg_iterations;    /* PCG iterations of the last solve, summed over GN iterations */
+  double scale;             /* s = exp(tau) after the last solve */
+  double cg_rel_residual;   /* ||r|| / ||b|| at the end of the last PCG solve (tolerance mode) */
+} kf_frame_stats;
+
+/* Fills *cfg with the defaults of the readings documented with the library:
+   n_samples 32, LINE5, n_gn 10, n_cg 20, cg_rtol 0, cg_max 4000, huber 1.345,
+   d_near 0.4, d_far 10, grad_gate 6, sigma_photo 1, r_floor 1e-6, KF_F32,
+   fx = fy = 0.8 width, cx = width / 2, cy = height / 2. */
+void kf_config_default(kf_config* cfg, int32_t width, int32_t height);
+
+/* Device bytes a context with this configuration needs; 0 if cfg is invalid. */
+size_t kf_workspace_bytes(const kf_config* cfg);
+
+/* Validates cfg and binds the workspace. No device work. *out = NULL on error. */
+kf_status kf_create(const kf_config* cfg, kf_ctx** out);
+
+/* Frees the host-side context (not the workspace). NULL is allowed. */
+void kf_destroy(kf_ctx* ctx);
+
+/* Message of the last failure on ctx ("" if none); static text if ctx is NULL. */
+const char* kf_last_error(const kf_ctx* ctx);
+
+/* Name of a status code. */
+const char* kf_status_string(int32_t status);
+
+/* New keyframe (Sec. II): the keyframe image (device uint8, H x W), the network's
+   log-depth and its variance, the x / y log-depth gradients and their variances
+   (device, map element type), and the keyframe pose (host double[16]).
+   Resets the state: log-depth x := prior log-depth, scale := 1, semi-dense filter
+   empty; computes the texture mask (grad_gate, 2-pixel border). */
+kf_status kf_set_prior(kf_ctx* ctx, const uint8_t* image0,
+                       const void* logdepth, const void* logdepth_var,
+                       const void* grad_x, const void* grad_x_var,
+                       const void* grad_y, const void* grad_y_var,
+                       const double T_wc0[16]);
+
+/* Semi-dense update only (Sec. II-B) with a new frame (device uint8 image, host pose). */
+kf_status kf_stereo_update(kf_ctx* ctx, const uint8_t* image1, const double T_wc1[16]);
+
+/* Optimisation only (Sec. II-C): n_gn Gauss-Newton iterations from the current state. */
+kf_status kf_solve(kf_ctx* ctx);
+
+/* The per-frame update: kf_stereo_update followed by kf_solve. */
+kf_status kf_fuse_frame(kf_ctx* ctx, const uint8_t* image1, const double T_wc1[16]);
+
+/* Writes depth = exp(x) (device, H x W, map element type) and, if var_out is not
+   NULL, the inverse-depth filter variance (0 where no estimate); *scale_out (host,
+   nullable) receives s. Synchronises the stream; returns a pending device error. */
+kf_status kf_read_depth(kf_ctx* ctx, void* depth_out, void* var_out, double* scale_out);
+
+/* Statistics of the last stereo update and solve (host struct). Synchronises. */
+kf_status kf_read_stats(kf_ctx* ctx, kf_frame_stats* out);
+
+/* Copies the resident state out (device buffers, each nullable): log-depth x,
+   inverse depth rho and its variance (0 = no estimate), the last match index per
+   pixel (int32: -2 = not textured, -1 = searched without a valid sample), and
+   tau = ln s (host). Synchronises. */
+kf_status kf_export_state(kf_ctx* ctx, void* x, void* rho, void* rho_var, int32_t* match,
+                          double* tau);
+
+/* Overwrites parts of the resident state (device buffers, each nullable; tau
+   host, nullable). Requires kf_set_prior first. Synchronises. */
+kf_status kf_import_state(kf_ctx* ctx, const void* x, const void* rho, const void* rho_var,
+                          const double* tau);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KF_H */

@@ -1,0 +1,537 @@
+// C ABI of the keyframe depth-update library: validation, workspace layout,
+// per-frame epipolar constants (host FP64) and kernel launches.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "kf_internal.h"
+
+struct kf_ctx {
+  kf_config cfg;
+  kf::Tiling tiling;
+  kf::Layout lay;
+  hipStream_t stream;
+  int device;
+  uint32_t epoch;
+  uint32_t frame;
+  bool has_prior;
+  double T_wc0[16];
+  std::string err;
+  char* ws;
+  uint64_t timeout_ticks;
+  int stereo_blocks;
+};
+
+namespace kf {
+
+namespace {
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+const char* validate(const kf_config& c) {
+  if (c.width < 8 || c.height < 8 || c.width > 8192 || c.height > 8192) return "width/height must be in [8, 8192]";
+  if (!finite_pos(c.fx) || !finite_pos(c.fy) || !std::isfinite(c.cx) || !std::isfinite(c.cy))
+    return "intrinsics must be finite with fx, fy > 0";
+  if (!is_pow2(c.n_samples) || c.n_samples < 4 || c.n_samples > 1024)
+    return "n_samples must be a power of two in [4, 1024]";
+  if (c.pattern != KF_PAT_LINE5 && c.pattern != KF_PAT_SQ5X5) return "pattern must be KF_PAT_LINE5 or KF_PAT_SQ5X5";
+  if (c.n_gn < 1 || c.n_gn > 1000) return "n_gn must be in [1, 1000]";
+  if (c.n_cg < 1 || c.n_cg > 100000) return "n_cg must be in [1, 100000]";
+  if (!(c.cg_rtol >= 0.0) || !std::isfinite(c.cg_rtol)) return "cg_rtol must be finite and >= 0";
+  if (c.cg_max < 1 || c.cg_max > 100000) return "cg_max must be in [1, 100000]";
+  if (!(c.huber_delta > 0.0)) return "huber_delta must be > 0 (INFINITY allowed)";
+  if (!finite_pos(c.d_near) || !finite_pos(c.d_far) || !(c.d_near < c.d_far)) return "need 0 < d_near < d_far";
+  if (!(c.grad_gate >= 0.0) || !std::isfinite(c.grad_gate)) return "grad_gate must be finite and >= 0";
+  if (!finite_pos(c.sigma_photo)) return "sigma_photo must be finite and > 0";
+  if (!finite_pos(c.r_floor)) return "r_floor must be finite and > 0";
+  if (c.precision != KF_F64 && c.precision != KF_F32 && c.precision != KF_BF16_F32) return "unknown precision";
+  if ((c.solver_tiles_x == 0) != (c.solver_tiles_y == 0) || c.solver_tiles_x < 0 || c.solver_tiles_y < 0)
+    return "solver_tiles_x/y must both be 0 (automatic) or both positive";
+  return nullptr;
+}
+
+int ppt_for(int px) {
+  const int need = (px + SOLVE_THREADS - 1) / SOLVE_THREADS;
+  static const int opts[] = {1, 2, 3, 4, 5, 6, 8};
+  for (int o : opts)
+    if (o >= need) return o;
+  return 0;
+}
+
+bool tiling_ok(int W, int H, int tx, int ty, Tiling* t) {
+  if (tx < 1 || ty < 1 || tx > W || ty > H || tx * ty > 1024) return false;
+  const int tw = (W + tx - 1) / tx, th = (H + ty - 1) / ty;
+  if ((tx - 1) * tw >= W || (ty - 1) * th >= H) return false;   // no empty tiles
+  if (tw + th > 1024) return false;                             // ghost ring fits the slots
+  const int ppt = ppt_for(tw * th);
+  if (ppt == 0) return false;
+  t->tiles_x = tx;
+  t->tiles_y = ty;
+  t->tile_w = tw;
+  t->tile_h = th;
+  t->blocks = tx * ty;
+  t->ppt = ppt;
+  return true;
+}
+
+}  // namespace
+
+// Picks the tile grid minimising a latency model of one PCG iteration:
+// team synchronisation ~1.1 us + 6.5 ns per workgroup (measured on MI355X)
+// plus the per-workgroup stencil work (~30 VALU ops per pixel at 64 lanes per
+// clock, 2.4 GHz), with a small penalty for long tile perimeters.
+bool choose_tiling(int W, int H, int tx_req, int ty_req, Tiling* t) {
+  if (tx_req > 0 && ty_req > 0) return tiling_ok(W, H, tx_req, ty_req, t);
+  double best = 1e300;
+  Tiling bt{};
+  bool found = false;
+  for (int tx = 1; tx <= 64 && tx <= W; ++tx) {
+    for (int ty = 1; ty <= 64 && ty <= H; ++ty) {
+      if (tx * ty > 256) break;
+      Tiling c;
+      if (!tiling_ok(W, H, tx, ty, &c)) continue;
+      const double sync_us = 1.1 + 0.0065 * c.blocks;
+      const double work_us = (double)c.tile_w * c.tile_h * 30.0 / 64.0 / 2400.0;
+      const double perim_us = (c.tile_w + c.tile_h) * 1e-4;
+      const double cost = sync_us + work_us + perim_us;
+      if (cost < best) {
+        best = cost;
+        bt = c;
+        found = true;
+      }
+    }
+  }
+  if (found) *t = bt;
+  return found;
+}
+
+bool layout_for(const kf_config& c, const Tiling& t, Layout* L) {
+  const size_t N = (size_t)c.width * c.height;
+  const size_t elt = c.precision == KF_F64 ? 8 : 4;
+  const size_t elt_img = c.precision == KF_F64 ? 8 : (c.precision == KF_F32 ? 4 : 2);
+  const size_t nchunks = (N + CHUNK - 1) / CHUNK;
+  size_t off = 0;
+  L->elt = elt;
+  L->elt_img = elt_img;
+  L->i0 = off; off += align256(N * elt_img);
+  L->list = off; off += align256(N * 4);
+  L->chunk = off; off += align256((nchunks + 1) * 4);
+  L->prior = off; off += align256(6 * N * elt);
+  L->x = off; off += align256(N * elt);
+  L->rho = off; off += align256(N * elt);
+  L->var = off; off += align256(N * elt);
+  L->match = off; off += align256(N * 4);
+  L->scal = off; off += 256;
+  L->parts = off; off += align256((size_t)2 * NV_MAX * t.blocks * 2 * 8);
+  L->halo = off; off += align256((size_t)2 * t.blocks * (2 * t.tile_w + 2 * t.tile_h) * 2 * 8);
+  L->total = off;
+  return true;
+}
+
+}  // namespace kf
+
+using namespace kf;
+
+namespace {
+
+kf_status fail(kf_ctx* ctx, kf_status s, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return s;
+}
+
+kf_status hip_fail(kf_ctx* ctx, hipError_t e, const char* where) {
+  return fail(ctx, KF_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+template <typename P>
+P* ws_ptr(kf_ctx* c, size_t off) { return reinterpret_cast<P*>(c->ws + off); }
+
+DevScalars* scal_ptr(kf_ctx* c) { return ws_ptr<DevScalars>(c, c->lay.scal); }
+
+// General 4x4 inverse (Gauss-Jordan, partial pivoting), row-major.
+bool inv4(const double* m, double* out) {
+  double a[4][8];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 8; ++j) a[i][j] = j < 4 ? m[i * 4 + j] : (j - 4 == i ? 1.0 : 0.0);
+  for (int c = 0; c < 4; ++c) {
+    int p = c;
+    for (int r = c + 1; r < 4; ++r)
+      if (std::fabs(a[r][c]) > std::fabs(a[p][c])) p = r;
+    if (a[p][c] == 0.0) return false;
+    if (p != c)
+      for (int j = 0; j < 8; ++j) std::swap(a[p][j], a[c][j]);
+    const double d = a[c][c];
+    for (int j = 0; j < 8; ++j) a[c][j] /= d;
+    for (int r = 0; r < 4; ++r) {
+      if (r == c) continue;
+      const double f = a[r][c];
+      if (f == 0.0) continue;
+      for (int j = 0; j < 8; ++j) a[r][j] -= f * a[c][j];
+    }
+  }
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) out[i * 4 + j] = a[i][j + 4];
+  return true;
+}
+
+bool pose_ok(const double* T) {
+  if (!T) return false;
+  for (int i = 0; i < 16; ++i)
+    if (!std::isfinite(T[i])) return false;
+  return T[12] == 0.0 && T[13] == 0.0 && T[14] == 0.0 && T[15] == 1.0;
+}
+
+// Epipolar constants of the photometric error (Sec. II-B): [R|t] = T_WC1^-1 T_WC0,
+// H = K R K^-1, b = K t, keyframe epipole K (-R^T t).
+bool frame_constants(const kf_ctx* c, const double* T1, FrameConst* fc) {
+  double T1i[16];
+  if (!inv4(T1, T1i)) return false;
+  double T[16];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < 4; ++k) s += T1i[i * 4 + k] * c->T_wc0[k * 4 + j];
+      T[i * 4 + j] = s;
+    }
+  const kf_config& g = c->cfg;
+  const double K[9] = {g.fx, 0, g.cx, 0, g.fy, g.cy, 0, 0, 1};
+  const double Ki[9] = {1.0 / g.fx, 0, -g.cx / g.fx, 0, 1.0 / g.fy, -g.cy / g.fy, 0, 0, 1};
+  double R[9], t[3];
+  for (int i = 0; i < 3; ++i) {
+    for (int j = 0; j < 3; ++j) R[i * 3 + j] = T[i * 4 + j];
+    t[i] = T[i * 4 + 3];
+  }
+  double KR[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < 3; ++k) s += K[i * 3 + k] * R[k * 3 + j];
+      KR[i * 3 + j] = s;
+    }
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < 3; ++k) s += KR[i * 3 + k] * Ki[k * 3 + j];
+      fc->Hm[i * 3 + j] = s;
+    }
+  double c1[3];
+  for (int i = 0; i < 3; ++i) {
+    double s = 0.0, s2 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      s += K[i * 3 + k] * t[k];
+      s2 -= R[k * 3 + i] * t[k];
+    }
+    fc->b[i] = s;
+    c1[i] = s2;
+  }
+  for (int i = 0; i < 3; ++i) {
+    double s = 0.0;
+    for (int k = 0; k < 3; ++k) s += K[i * 3 + k] * c1[k];
+    fc->e0[i] = s;
+  }
+  fc->rho_min = 1.0 / g.d_far;
+  fc->rho_max = 1.0 / g.d_near;
+  fc->sigma_photo = g.sigma_photo;
+  return true;
+}
+
+kf_status check_device_flags(kf_ctx* c) {
+  DevScalars h;
+  hipError_t e = hipMemcpyAsync(&h, scal_ptr(c), sizeof(h), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "synchronising the stream");
+  if (h.err & ERR_TIMEOUT) return fail(c, KF_ERR_TIMEOUT, "solver workgroups timed out waiting for their team");
+  if (h.err & ERR_INPUT) return fail(c, KF_ERR_INPUT, "device found a non-finite input or a variance <= 0");
+  return KF_OK;
+}
+
+}  // namespace
+
+namespace kf {
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+}
+
+extern "C" {
+
+void kf_config_default(kf_config* cfg, int32_t width, int32_t height) {
+  if (!cfg) return;
+  std::memset(cfg, 0, sizeof(*cfg));
+  cfg->width = width;
+  cfg->height = height;
+  cfg->fx = cfg->fy = 0.8 * width;
+  cfg->cx = width / 2.0;
+  cfg->cy = height / 2.0;
+  cfg->n_samples = 32;
+  cfg->pattern = KF_PAT_LINE5;
+  cfg->n_gn = 10;
+  cfg->n_cg = 20;
+  cfg->cg_rtol = 0.0;
+  cfg->cg_max = 4000;
+  cfg->huber_delta = 1.345;
+  cfg->d_near = 0.4;
+  cfg->d_far = 10.0;
+  cfg->grad_gate = 6.0;
+  cfg->sigma_photo = 1.0;
+  cfg->r_floor = 1e-6;
+  cfg->precision = KF_F32;
+}
+
+size_t kf_workspace_bytes(const kf_config* cfg) {
+  if (!cfg || validate(*cfg)) return 0;
+  Tiling t;
+  if (!choose_tiling(cfg->width, cfg->height, cfg->solver_tiles_x, cfg->solver_tiles_y, &t)) return 0;
+  Layout L;
+  layout_for(*cfg, t, &L);
+  return L.total;
+}
+
+kf_status kf_create(const kf_config* cfg, kf_ctx** out) {
+  if (!out) return KF_ERR_ARG;
+  *out = nullptr;
+  if (!cfg) return KF_ERR_ARG;
+  if (validate(*cfg)) return KF_ERR_ARG;
+  Tiling t;
+  if (!choose_tiling(cfg->width, cfg->height, cfg->solver_tiles_x, cfg->solver_tiles_y, &t)) return KF_ERR_ARG;
+  Layout L;
+  layout_for(*cfg, t, &L);
+  if (!cfg->workspace) return KF_ERR_ARG;
+  if (cfg->workspace_bytes < L.total) return KF_ERR_OOM;
+  if (reinterpret_cast<uintptr_t>(cfg->workspace) % 256 != 0) return KF_ERR_ARG;
+  kf_ctx* c = new (std::nothrow) kf_ctx();
+  if (!c) return KF_ERR_OOM;
+  c->cfg = *cfg;
+  c->tiling = t;
+  c->lay = L;
+  c->stream = reinterpret_cast<hipStream_t>(cfg->stream);
+  c->ws = reinterpret_cast<char*>(cfg->workspace);
+  c->epoch = 1;
+  c->frame = 0;
+  c->has_prior = false;
+  if (hipGetDevice(&c->device) != hipSuccess) c->device = 0;
+  int rate_khz = 100000;
+  if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, c->device) != hipSuccess || rate_khz <= 0)
+    rate_khz = 100000;
+  c->timeout_ticks = (uint64_t)rate_khz * 1000ull * 2ull;   // 2 s
+  c->stereo_blocks = stereo_grid_blocks(c->device);
+  *out = c;
+  return KF_OK;
+}
+
+void kf_destroy(kf_ctx* ctx) { delete ctx; }
+
+const char* kf_last_error(const kf_ctx* ctx) {
+  if (!ctx) return "no context";
+  return ctx->err.c_str();
+}
+
+const char* kf_status_string(int32_t s) {
+  switch (s) {
+    case KF_OK: return "KF_OK";
+    case KF_ERR_ARG: return "KF_ERR_ARG";
+    case KF_ERR_OOM: return "KF_ERR_OOM";
+    case KF_ERR_HIP: return "KF_ERR_HIP";
+    case KF_ERR_STATE: return "KF_ERR_STATE";
+    case KF_ERR_INPUT: return "KF_ERR_INPUT";
+    case KF_ERR_TIMEOUT: return "KF_ERR_TIMEOUT";
+  }
+  return "unknown status";
+}
+
+kf_status kf_set_prior(kf_ctx* c, const uint8_t* image0, const void* logdepth, const void* logdepth_var,
+                       const void* grad_x, const void* grad_x_var, const void* grad_y, const void* grad_y_var,
+                       const double T_wc0[16]) {
+  if (!c) return KF_ERR_ARG;
+  if (!image0 || !logdepth || !logdepth_var || !grad_x || !grad_x_var || !grad_y || !grad_y_var)
+    return fail(c, KF_ERR_ARG, "kf_set_prior: NULL buffer");
+  if (!pose_ok(T_wc0)) return fail(c, KF_ERR_ARG, "kf_set_prior: pose must be finite with last row 0 0 0 1");
+  std::memcpy(c->T_wc0, T_wc0, sizeof(c->T_wc0));
+  // exchange words and device scalars start from zero (epoch 0 is never used)
+  hipError_t e = launch_zero(c->ws + c->lay.scal, c->lay.total - c->lay.scal, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "kf_set_prior (clear)");
+  c->epoch = 1;
+  PriorArgs a;
+  a.W = c->cfg.width;
+  a.H = c->cfg.height;
+  a.image0 = image0;
+  a.mu = logdepth; a.var_n = logdepth_var; a.gx = grad_x; a.var_gx = grad_x_var; a.gy = grad_y; a.var_gy = grad_y_var;
+  a.i0 = c->ws + c->lay.i0;
+  a.prior = c->ws + c->lay.prior;
+  a.x = c->ws + c->lay.x;
+  a.rho = c->ws + c->lay.rho;
+  a.var = c->ws + c->lay.var;
+  a.match = ws_ptr<int32_t>(c, c->lay.match);
+  a.chunk_counts = ws_ptr<int32_t>(c, c->lay.chunk);
+  a.list = ws_ptr<int32_t>(c, c->lay.list);
+  a.scal = scal_ptr(c);
+  a.grad_gate = c->cfg.grad_gate;
+  a.border = 2;
+  e = launch_prior(c->cfg.precision, a, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "kf_set_prior");
+  c->has_prior = true;
+  c->err.clear();
+  return KF_OK;
+}
+
+kf_status kf_stereo_update(kf_ctx* c, const uint8_t* image1, const double T_wc1[16]) {
+  if (!c) return KF_ERR_ARG;
+  if (!c->has_prior) return fail(c, KF_ERR_STATE, "kf_stereo_update before kf_set_prior");
+  if (!image1) return fail(c, KF_ERR_ARG, "kf_stereo_update: NULL image");
+  if (!pose_ok(T_wc1)) return fail(c, KF_ERR_ARG, "kf_stereo_update: pose must be finite with last row 0 0 0 1");
+  StereoArgs a;
+  if (!frame_constants(c, T_wc1, &a.fc)) return fail(c, KF_ERR_ARG, "kf_stereo_update: singular pose");
+  a.W = c->cfg.width;
+  a.H = c->cfg.height;
+  a.i0 = c->ws + c->lay.i0;
+  a.i1 = image1;
+  a.list = ws_ptr<int32_t>(c, c->lay.list);
+  a.scal_ro = scal_ptr(c);
+  a.scal = scal_ptr(c);
+  a.rho = c->ws + c->lay.rho;
+  a.var = c->ws + c->lay.var;
+  a.match = ws_ptr<int32_t>(c, c->lay.match);
+  hipError_t e = launch_zero(&scal_ptr(c)->n_updated, sizeof(int32_t), c->stream);
+  if (e == hipSuccess)
+    e = launch_stereo(c->cfg.precision, c->cfg.pattern, c->cfg.n_samples, a, c->stereo_blocks, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "kf_stereo_update");
+  ++c->frame;
+  return KF_OK;
+}
+
+kf_status kf_solve(kf_ctx* c) {
+  if (!c) return KF_ERR_ARG;
+  if (!c->has_prior) return fail(c, KF_ERR_STATE, "kf_solve before kf_set_prior");
+  const kf_config& g = c->cfg;
+  const uint64_t limit = g.cg_rtol > 0.0 ? (uint64_t)g.cg_max : (uint64_t)g.n_cg;
+  const uint64_t bound = (uint64_t)g.n_gn * (2 * limit + 2) + 2;
+  if ((uint64_t)c->epoch + bound >= 0xfff00000ull) {
+    hipError_t e = launch_zero(c->ws + c->lay.parts, c->lay.total - c->lay.parts, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "kf_solve (epoch wrap)");
+    c->epoch = 1;
+  }
+  SolveArgs a;
+  a.W = g.width;
+  a.H = g.height;
+  a.tiles_x = c->tiling.tiles_x;
+  a.tiles_y = c->tiling.tiles_y;
+  a.tile_w = c->tiling.tile_w;
+  a.tile_h = c->tiling.tile_h;
+  a.prior = c->ws + c->lay.prior;
+  a.rho = c->ws + c->lay.rho;
+  a.var = c->ws + c->lay.var;
+  a.x = c->ws + c->lay.x;
+  a.scal = scal_ptr(c);
+  a.parts = ws_ptr<uint64_t>(c, c->lay.parts);
+  a.halo = ws_ptr<uint64_t>(c, c->lay.halo);
+  a.perim = 2 * c->tiling.tile_w + 2 * c->tiling.tile_h;
+  a.epoch0 = c->epoch;
+  a.n_gn = g.n_gn;
+  a.n_cg = g.n_cg;
+  a.cg_max = g.cg_max;
+  a.cg_rtol = g.cg_rtol;
+  a.huber_delta = g.huber_delta;
+  a.r_floor = g.r_floor;
+  a.timeout_ticks = c->timeout_ticks;
+  hipError_t e = launch_solve(g.precision, c->tiling, a, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "kf_solve");
+  c->epoch += (uint32_t)bound;
+  return KF_OK;
+}
+
+kf_status kf_fuse_frame(kf_ctx* c, const uint8_t* image1, const double T_wc1[16]) {
+  kf_status s = kf_stereo_update(c, image1, T_wc1);
+  if (s != KF_OK) return s;
+  return kf_solve(c);
+}
+
+kf_status kf_read_depth(kf_ctx* c, void* depth_out, void* var_out, double* scale_out) {
+  if (!c) return KF_ERR_ARG;
+  if (!c->has_prior) return fail(c, KF_ERR_STATE, "kf_read_depth before kf_set_prior");
+  if (depth_out || var_out) {
+    if (!depth_out) return fail(c, KF_ERR_ARG, "kf_read_depth: var_out needs depth_out");
+    ReadArgs a;
+    a.N = c->cfg.width * c->cfg.height;
+    a.x = c->ws + c->lay.x;
+    a.var = c->ws + c->lay.var;
+    a.depth_out = depth_out;
+    a.var_out = var_out;
+    hipError_t e = launch_read(c->cfg.precision, a, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "kf_read_depth");
+  }
+  kf_status s = check_device_flags(c);
+  if (s != KF_OK) return s;
+  if (scale_out) {
+    double tau;
+    hipError_t e = hipMemcpy(&tau, &scal_ptr(c)->tau, sizeof(double), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(c, e, "kf_read_depth (scale)");
+    *scale_out = std::exp(tau);
+  }
+  return KF_OK;
+}
+
+kf_status kf_read_stats(kf_ctx* c, kf_frame_stats* out) {
+  if (!c || !out) return KF_ERR_ARG;
+  if (!c->has_prior) return fail(c, KF_ERR_STATE, "kf_read_stats before kf_set_prior");
+  DevScalars h;
+  hipError_t e = hipMemcpyAsync(&h, scal_ptr(c), sizeof(h), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "kf_read_stats");
+  out->n_searched = h.mask_count;
+  out->n_updated = h.n_updated;
+  out->n_valid = h.n_valid;
+  out->cg_iterations = h.cg_iterations;
+  out->scale = std::exp(h.tau);
+  out->cg_rel_residual = h.cg_rel_residual;
+  if (h.err & ERR_TIMEOUT) return fail(c, KF_ERR_TIMEOUT, "solver workgroups timed out waiting for their team");
+  if (h.err & ERR_INPUT) return fail(c, KF_ERR_INPUT, "device found a non-finite input or a variance <= 0");
+  return KF_OK;
+}
+
+kf_status kf_export_state(kf_ctx* c, void* x, void* rho, void* rho_var, int32_t* match, double* tau) {
+  if (!c) return KF_ERR_ARG;
+  if (!c->has_prior) return fail(c, KF_ERR_STATE, "kf_export_state before kf_set_prior");
+  const size_t N = (size_t)c->cfg.width * c->cfg.height;
+  const size_t nb = N * c->lay.elt;
+  hipError_t e = hipSuccess;
+  if (x && e == hipSuccess) e = hipMemcpyAsync(x, c->ws + c->lay.x, nb, hipMemcpyDeviceToDevice, c->stream);
+  if (rho && e == hipSuccess) e = hipMemcpyAsync(rho, c->ws + c->lay.rho, nb, hipMemcpyDeviceToDevice, c->stream);
+  if (rho_var && e == hipSuccess)
+    e = hipMemcpyAsync(rho_var, c->ws + c->lay.var, nb, hipMemcpyDeviceToDevice, c->stream);
+  if (match && e == hipSuccess)
+    e = hipMemcpyAsync(match, c->ws + c->lay.match, N * 4, hipMemcpyDeviceToDevice, c->stream);
+  double t = 0.0;
+  if (tau && e == hipSuccess) e = hipMemcpyAsync(&t, &scal_ptr(c)->tau, 8, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "kf_export_state");
+  if (tau) *tau = t;
+  return KF_OK;
+}
+
+kf_status kf_import_state(kf_ctx* c, const void* x, const void* rho, const void* rho_var, const double* tau) {
+  if (!c) return KF_ERR_ARG;
+  if (!c->has_prior) return fail(c, KF_ERR_STATE, "kf_import_state before kf_set_prior");
+  if ((rho == nullptr) != (rho_var == nullptr)) return fail(c, KF_ERR_ARG, "kf_import_state: rho and rho_var go together");
+  if (tau && !std::isfinite(*tau)) return fail(c, KF_ERR_ARG, "kf_import_state: tau must be finite");
+  hipError_t e = hipSuccess;
+  if (x || rho) {
+    ImportArgs a;
+    a.N = c->cfg.width * c->cfg.height;
+    a.x = x; a.rho = rho; a.var = rho_var;
+    a.dx = c->ws + c->lay.x;
+    a.drho = c->ws + c->lay.rho;
+    a.dvar = c->ws + c->lay.var;
+    a.scal = scal_ptr(c);
+    e = launch_import(c->cfg.precision, a, c->stream);
+  }
+  double t = tau ? *tau : 0.0;
+  if (tau && e == hipSuccess) e = hipMemcpyAsync(&scal_ptr(c)->tau, &t, 8, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "kf_import_state");
+  return check_device_flags(c);
+}
+
+}  // extern "C"

@@ -1,0 +1,165 @@
+// Internal declarations of the keyframe depth-update library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "kf.h"
+
+namespace kf {
+
+// ------------------------------------------------------------------ storage types
+
+// bfloat16 stored as its 16 raw bits; conversions round to nearest even.
+struct bf16 {
+  uint16_t bits;
+};
+
+__host__ __device__ inline float bf16_to_float(bf16 h) {
+  union { uint32_t u; float f; } c;
+  c.u = (uint32_t)h.bits << 16;
+  return c.f;
+}
+
+__host__ __device__ inline bf16 float_to_bf16(float f) {
+  union { uint32_t u; float f; } c;
+  c.f = f;
+  uint32_t u = c.u;
+  bf16 h;
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) {
+    h.bits = (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
+  } else {
+    u += 0x7fffu + ((u >> 16) & 1u);
+    h.bits = (uint16_t)(u >> 16);
+  }
+  return h;
+}
+
+template <typename TI, typename T> __device__ inline T load_img(const TI* p, size_t i);
+template <> __device__ inline double load_img<double, double>(const double* p, size_t i) { return p[i]; }
+template <> __device__ inline float load_img<float, float>(const float* p, size_t i) { return p[i]; }
+template <> __device__ inline float load_img<bf16, float>(const bf16* p, size_t i) { return bf16_to_float(p[i]); }
+
+template <typename TI, typename T> __device__ inline TI to_img(T v);
+template <> __device__ inline double to_img<double, double>(double v) { return v; }
+template <> __device__ inline float to_img<float, float>(float v) { return v; }
+template <> __device__ inline bf16 to_img<bf16, float>(float v) { return float_to_bf16(v); }
+
+// Form traits: T = map and arithmetic type, TI = keyframe image / patch storage type.
+template <int PREC> struct Form;
+template <> struct Form<KF_F64> { using T = double; using TI = double; };
+template <> struct Form<KF_F32> { using T = float; using TI = float; };
+template <> struct Form<KF_BF16_F32> { using T = float; using TI = bf16; };
+
+// ------------------------------------------------------------------ device scalars block
+
+// Device-side counters and flags (one 256-byte block in the workspace).
+struct DevScalars {
+  double tau;             // ln s
+  double cg_rel_residual;
+  int32_t mask_count;     // textured pixels (length of the search list)
+  int32_t n_updated;      // measurements produced by the last stereo update
+  int32_t n_valid;        // pixels with a filter estimate (computed by the solver)
+  int32_t cg_iterations;
+  int32_t err;            // bit flags, ERR_*
+  int32_t pad[7];
+};
+enum : int32_t { ERR_INPUT = 1, ERR_TIMEOUT = 2 };
+
+// ------------------------------------------------------------------ workspace layout
+
+struct Layout {
+  size_t i0, list, chunk, prior, x, rho, var, match, scal, parts, halo, total;
+  size_t elt;       // sizeof(T)
+  size_t elt_img;   // sizeof(TI)
+};
+
+// Solver decomposition: tiles_x x tiles_y workgroups, each owning one tile.
+struct Tiling {
+  int tiles_x, tiles_y, tile_w, tile_h, blocks, ppt;
+};
+
+constexpr int SOLVE_THREADS = 256;
+constexpr int NV_MAX = 3;            // values reduced per synchronisation
+constexpr int CHUNK = 256;           // pixels per compaction chunk
+
+bool choose_tiling(int W, int H, int tx_req, int ty_req, Tiling* t);
+bool layout_for(const kf_config& cfg, const Tiling& t, Layout* lay);
+
+// ------------------------------------------------------------------ kernel arguments
+
+struct PriorArgs {
+  int W, H;
+  const uint8_t* image0;
+  const void* mu; const void* var_n; const void* gx; const void* var_gx; const void* gy; const void* var_gy;
+  void* i0;                  // TI[N]
+  void* prior;               // T[6][N]: mu, isd_n, gx, isd_gx, gy, isd_gy (isd = 1/sigma)
+  void* x; void* rho; void* var; int32_t* match;
+  int32_t* chunk_counts;     // [nchunks + 1]
+  int32_t* list;             // [N]
+  DevScalars* scal;
+  double grad_gate;
+  int border;
+};
+
+struct FrameConst {          // epipolar constants of one frame (host FP64)
+  double Hm[9];              // K R K^-1
+  double b[3];               // K t
+  double e0[3];              // keyframe epipole K c1 (homogeneous)
+  double rho_min, rho_max;
+  double sigma_photo;
+};
+
+struct StereoArgs {
+  int W, H;
+  const void* i0;            // TI[N]
+  const uint8_t* i1;         // new frame
+  const int32_t* list;
+  const DevScalars* scal_ro;
+  DevScalars* scal;
+  void* rho; void* var; int32_t* match;
+  FrameConst fc;
+};
+
+struct SolveArgs {
+  int W, H;
+  int tiles_x, tiles_y, tile_w, tile_h;
+  const void* prior;         // T[6][N]
+  const void* rho; const void* var;
+  void* x;
+  DevScalars* scal;
+  uint64_t* parts;           // [2][NV_MAX][blocks][2] exchange words
+  uint64_t* halo;            // [2][blocks][perim][2]
+  int perim;                 // 2 tile_w + 2 tile_h
+  uint32_t epoch0;
+  int n_gn, n_cg, cg_max;
+  double cg_rtol;
+  double huber_delta, r_floor;
+  uint64_t timeout_ticks;    // wall-clock ticks a workgroup may wait for its team
+};
+
+struct ReadArgs {
+  int N;
+  const void* x; const void* var;
+  void* depth_out; void* var_out;
+};
+
+struct ImportArgs {
+  int N;
+  const void* x; const void* rho; const void* var;
+  void* dx; void* drho; void* dvar;
+  DevScalars* scal;
+};
+
+// ------------------------------------------------------------------ launchers (return hipError_t)
+
+hipError_t launch_prior(int prec, const PriorArgs& a, hipStream_t s);
+hipError_t launch_stereo(int prec, int pattern, int ns, const StereoArgs& a, int blocks, hipStream_t s);
+hipError_t launch_solve(int prec, const Tiling& t, const SolveArgs& a, hipStream_t s);
+hipError_t launch_read(int prec, const ReadArgs& a, hipStream_t s);
+hipError_t launch_import(int prec, const ImportArgs& a, hipStream_t s);
+size_t solve_smem_bytes(int prec, const Tiling& t);
+int stereo_grid_blocks(int device);
+
+}  // namespace kf

@@ -1,0 +1,514 @@
+// Optimisation (Sec. II-C): n_gn Gauss-Newton iterations alternating between the
+// log-depth map x and the scale tau = ln s, each depth step solved by Jacobi-
+// preconditioned CG on the 5-point normal equations, all in ONE persistent,
+// cooperatively launched kernel.
+//
+// Decomposition: the keyframe is cut into tiles_x x tiles_y tiles; workgroup b
+// owns tile b for the whole launch and keeps its CG vectors in registers and a
+// one-pixel ghost ring of the stencil operand in LDS. Workgroups never meet at
+// a grid barrier. At each synchronisation point every workgroup publishes its
+// partial sums and its tile boundary as 64-bit words tagged with an epoch
+// number (relaxed agent-scope atomic stores), then polls the words it needs:
+// all partials of the team (summed in a fixed order, so every workgroup gets
+// bit-identical totals) and the boundaries of its four neighbours. Slots are
+// double-buffered by epoch parity; no workgroup can run two synchronisations
+// ahead of another because each one waits for every partial.
+//
+// Per GN iteration: 1 synchronisation for the initial residual, 2 per PCG
+// iteration (p.q; then r.z with the z boundary from which every workgroup
+// rebuilds its ghost copy of p), minus the last r.z in fixed-count mode, and 1
+// for the scale step (which also ships the x boundary).
+#include "kf_internal.h"
+
+namespace kf {
+
+namespace {
+
+constexpr int NT = SOLVE_THREADS;
+constexpr int NW = NT / 64;
+constexpr int GMAX = 8;      // ghost slots per thread: ghost ring <= GMAX * NT cells
+
+__device__ inline void st_word(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline uint64_t ld_word(const uint64_t* p) {
+  return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline uint64_t tagged(uint32_t bits, uint32_t e) { return ((uint64_t)e << 32) | (uint64_t)bits; }
+
+template <typename V> struct Wire;
+template <> struct Wire<float> {
+  static constexpr int N = 1;
+  __device__ static void put(uint64_t* w, float v, uint32_t e) { st_word(w, tagged(__float_as_uint(v), e)); }
+  __device__ static float make(uint32_t lo, uint32_t) { return __uint_as_float(lo); }
+};
+template <> struct Wire<double> {
+  static constexpr int N = 2;
+  __device__ static void put(uint64_t* w, double v, uint32_t e) {
+    const uint64_t bits = (uint64_t)__double_as_longlong(v);
+    st_word(w, tagged((uint32_t)bits, e));
+    st_word(w + 1, tagged((uint32_t)(bits >> 32), e));
+  }
+  __device__ static double make(uint32_t lo, uint32_t hi) {
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+  }
+};
+
+// Spin until the value at w carries epoch e; false on timeout or team abort.
+template <typename V>
+__device__ inline bool wait_get(const uint64_t* w, uint32_t e, V& out, uint64_t limit, const int32_t* err) {
+  uint32_t part[2] = {0u, 0u};
+  const uint64_t t0 = wall_clock64();
+#pragma unroll
+  for (int k = 0; k < Wire<V>::N; ++k) {
+    unsigned spins = 0;
+    uint64_t x;
+    while (true) {
+      x = ld_word(w + k);
+      if ((uint32_t)(x >> 32) == e) break;
+      if ((++spins & 255u) == 0u) {
+        if (wall_clock64() - t0 > limit) return false;
+        if (__hip_atomic_load(const_cast<int32_t*>(err), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
+            ERR_TIMEOUT)
+          return false;
+      }
+    }
+    part[k] = (uint32_t)x;
+  }
+  out = Wire<V>::make(part[0], part[1]);
+  return true;
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+template <typename T>
+__device__ inline T huber_w(T r, T delta) {
+  const T a = fabs(r);
+  return a <= delta ? (T)1 : delta / a;
+}
+
+// IRLS weight of the gradient edge between x_a and its right / lower neighbour x_b.
+template <typename T>
+__device__ inline T edge_weight(T xa, T xb, T g, T isd, T delta) {
+  const T r = ((xb - xa) - g) * isd;
+  return huber_w(r, delta) * isd * isd;
+}
+
+template <typename T>
+struct Team {
+  int B, b, tw, th, rw, perim, tile_w, tile_h;
+  int nb_up, nb_dn, nb_lf, nb_rt;
+  uint64_t* parts;
+  uint64_t* halo;
+  const int32_t* err;
+  int32_t* err_w;
+  uint64_t limit;
+  double* s_wred;   // [NW][NV_MAX]
+  double* s_pol;    // [NV_MAX][B]
+  double* s_tot;    // [NV_MAX]
+  int* s_abort;
+  // ghost slots of this thread
+  int g_src[GMAX];  // neighbour workgroup or -1
+  int g_off[GMAX];  // offset in its boundary list
+  int g_li[GMAX];   // ring index
+
+  __device__ uint64_t* part_slot(uint32_t e, int v, int j) const {
+    return parts + ((size_t)((e & 1u) * NV_MAX + v) * B + j) * 2;
+  }
+  __device__ uint64_t* halo_slot(uint32_t e, int blk, int off) const {
+    return halo + ((size_t)((e & 1u) * B + blk) * perim + off) * 2;
+  }
+
+  // Publishes the boundary value of own pixel (lx, ly) for the neighbours that read it.
+  __device__ void publish(uint32_t e, int lx, int ly, T val) const {
+    if (ly == 0 && nb_up >= 0) Wire<T>::put(halo_slot(e, b, lx), val, e);
+    if (ly == th - 1 && nb_dn >= 0) Wire<T>::put(halo_slot(e, b, tile_w + lx), val, e);
+    if (lx == 0 && nb_lf >= 0) Wire<T>::put(halo_slot(e, b, 2 * tile_w + ly), val, e);
+    if (lx == tw - 1 && nb_rt >= 0) Wire<T>::put(halo_slot(e, b, 2 * tile_w + tile_h + ly), val, e);
+  }
+
+  // Team-wide sums of nv per-thread partials (fixed summation order) and the
+  // neighbours' published boundary values for this thread's ghost slots.
+  // Returns false if the team has to abort (all threads agree).
+  __device__ bool sync(uint32_t e, int nv, const double* vals, double* tot, T* gval, bool ghosts) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int v = 0; v < nv; ++v) {
+      const double s = wave_sum(vals[v]);
+      if (lane == 0) s_wred[wave * NV_MAX + v] = s;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      for (int v = 0; v < nv; ++v) {
+        double p = 0.0;
+        for (int w = 0; w < NW; ++w) p += s_wred[w * NV_MAX + v];
+        Wire<double>::put(part_slot(e, v, b), p, e);
+      }
+    }
+    bool ok = true;
+    for (int s = tid; s < nv * B; s += NT) {
+      const int v = s / B, j = s - v * B;
+      double val = 0.0;
+      ok = ok && wait_get<double>(part_slot(e, v, j), e, val, limit, err);
+      s_pol[v * B + j] = val;
+    }
+#pragma unroll
+    for (int m = 0; m < GMAX; ++m) {
+      if (ghosts && g_src[m] >= 0) {
+        T val = (T)0;
+        ok = ok && wait_get<T>(halo_slot(e, g_src[m], g_off[m]), e, val, limit, err);
+        gval[m] = val;
+      }
+    }
+    if (!ok) {
+      *s_abort = 1;
+      atomicOr(err_w, ERR_TIMEOUT);
+    }
+    __syncthreads();
+    if (*s_abort) return false;
+    if (wave < nv) {
+      double acc = 0.0;
+      for (int j = lane; j < B; j += 64) acc += s_pol[wave * B + j];
+      acc = wave_sum(acc);
+      if (lane == 0) s_tot[wave] = acc;
+    }
+    __syncthreads();
+    for (int v = 0; v < nv; ++v) tot[v] = s_tot[v];
+    return true;
+  }
+};
+
+template <typename T, int PPT>
+__global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int B = a.tiles_x * a.tiles_y;
+  const int b = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int W = a.W, H = a.H, N = W * H;
+
+  Team<T> tm;
+  tm.B = B;
+  tm.b = b;
+  const int bx = b % a.tiles_x, by = b / a.tiles_x;
+  const int ox = bx * a.tile_w, oy = by * a.tile_h;
+  tm.tile_w = a.tile_w;
+  tm.tile_h = a.tile_h;
+  tm.tw = min(a.tile_w, W - ox);
+  tm.th = min(a.tile_h, H - oy);
+  tm.rw = tm.tw + 2;
+  tm.perim = a.perim;
+  tm.nb_up = by > 0 ? b - a.tiles_x : -1;
+  tm.nb_dn = by < a.tiles_y - 1 ? b + a.tiles_x : -1;
+  tm.nb_lf = bx > 0 ? b - 1 : -1;
+  tm.nb_rt = bx < a.tiles_x - 1 ? b + 1 : -1;
+  tm.parts = a.parts;
+  tm.halo = a.halo;
+  tm.err = &a.scal->err;
+  tm.err_w = &a.scal->err;
+  tm.limit = a.timeout_ticks;
+  double* dsm = reinterpret_cast<double*>(smem);
+  tm.s_wred = dsm;
+  tm.s_pol = tm.s_wred + NW * NV_MAX;
+  tm.s_tot = tm.s_pol + NV_MAX * B;
+  tm.s_abort = reinterpret_cast<int*>(tm.s_tot + NV_MAX);
+  const int ring_max = (a.tile_h + 2) * (a.tile_w + 2);
+  T* xs = reinterpret_cast<T*>(dsm + NW * NV_MAX + NV_MAX * B + NV_MAX + 2);
+  T* ps = xs + ring_max;
+
+  const int tw = tm.tw, th = tm.th, rw = tm.rw;
+  const int npx = tw * th;
+  const T delta = (T)a.huber_delta;
+
+  for (int i = tid; i < 2 * ring_max; i += NT) xs[i] = (T)0;
+  if (tid == 0) *tm.s_abort = 0;
+
+  // ghost slots: top row, bottom row, left column, right column
+  const int nghost = 2 * tw + 2 * th;
+#pragma unroll
+  for (int m = 0; m < GMAX; ++m) {
+    const int g = tid + m * NT;
+    tm.g_src[m] = -1;
+    tm.g_off[m] = 0;
+    tm.g_li[m] = 0;
+    if (g < nghost) {
+      if (g < tw) {
+        tm.g_src[m] = tm.nb_up; tm.g_off[m] = a.tile_w + g; tm.g_li[m] = g + 1;
+      } else if (g < 2 * tw) {
+        const int lx = g - tw;
+        tm.g_src[m] = tm.nb_dn; tm.g_off[m] = lx; tm.g_li[m] = (th + 1) * rw + lx + 1;
+      } else if (g < 2 * tw + th) {
+        const int ly = g - 2 * tw;
+        tm.g_src[m] = tm.nb_lf; tm.g_off[m] = 2 * a.tile_w + a.tile_h + ly; tm.g_li[m] = (ly + 1) * rw;
+      } else {
+        const int ly = g - 2 * tw - th;
+        tm.g_src[m] = tm.nb_rt; tm.g_off[m] = 2 * a.tile_w + ly; tm.g_li[m] = (ly + 1) * rw + tw + 1;
+      }
+    }
+  }
+  __syncthreads();
+
+  const T* pr = static_cast<const T*>(a.prior);
+  const T* mu_g = pr;
+  const T* isn_g = pr + (size_t)N;
+  const T* gx_g = pr + 2 * (size_t)N;
+  const T* isgx_g = pr + 3 * (size_t)N;
+  const T* gy_g = pr + 4 * (size_t)N;
+  const T* isgy_g = pr + 5 * (size_t)N;
+  T* x_g = static_cast<T*>(a.x);
+  const T* rho_g = static_cast<const T*>(a.rho);
+  const T* var_g = static_cast<const T*>(a.var);
+
+  // per-pixel registers
+  int gi[PPT], li[PPT], lxy[PPT];
+  bool own[PPT];
+  T xr[PPT], rr[PPT], pv[PPT], dg[PPT], idg[PPT], cR[PPT], cL[PPT], cD[PPT], cU[PPT], zs[PPT], isr[PPT];
+  const T r_floor = (T)a.r_floor;
+#pragma unroll
+  for (int j = 0; j < PPT; ++j) {
+    const int k = tid + j * NT;
+    own[j] = k < npx;
+    const int lx = own[j] ? k % tw : 0, ly = own[j] ? k / tw : 0;
+    lxy[j] = (ly << 16) | lx;
+    gi[j] = (oy + ly) * W + ox + lx;
+    li[j] = (ly + 1) * rw + lx + 1;
+    xr[j] = rr[j] = pv[j] = dg[j] = idg[j] = cR[j] = cL[j] = cD[j] = cU[j] = zs[j] = isr[j] = (T)0;
+    if (own[j]) {
+      xr[j] = x_g[gi[j]];
+      xs[li[j]] = xr[j];
+      // semi-dense measurement in log space (Sec. II-B last step): z = -ln rho, R = v / rho^2
+      const T v = var_g[gi[j]];
+      if (v > (T)0) {
+        const T rho = rho_g[gi[j]];
+        zs[j] = -log(rho);
+        T R = v / (rho * rho);
+        R = R > r_floor ? R : r_floor;
+        isr[j] = (T)1 / sqrt(R);
+      }
+    }
+  }
+  // ghost x straight from the state (consistent at launch)
+#pragma unroll
+  for (int m = 0; m < GMAX; ++m) {
+    if (tm.g_src[m] >= 0) {
+      const int li_g = tm.g_li[m];
+      const int gy_ = li_g / rw - 1, gx_ = li_g % rw - 1;
+      xs[li_g] = x_g[(oy + gy_) * W + ox + gx_];
+    }
+  }
+  double tau = a.scal->tau;
+  __syncthreads();
+
+  uint32_t e = a.epoch0;
+  const bool tol_mode = a.cg_rtol > 0.0;
+  const int limit = tol_mode ? a.cg_max : a.n_cg;
+  int cg_total = 0;
+  double relres = 0.0;
+  double n_valid = 0.0;
+  double vals[NV_MAX], tot[NV_MAX];
+  T gval[GMAX];
+
+  for (int gn = 0; gn < a.n_gn; ++gn) {
+    // ---- IRLS weights and 5-point normal equations at (x, tau) (Sec. II-C)
+    double rz = 0.0, r2 = 0.0, b2 = 0.0;
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      if (!own[j]) continue;
+      const int lx = lxy[j] & 0xffff, ly = lxy[j] >> 16;
+      const int u = ox + lx, v = oy + ly;
+      const int i = gi[j];
+      const T xi = xr[j];
+      const T mu = mu_g[i], isn = isn_g[i];
+      const T wn = huber_w((xi - mu) * isn, delta) * isn * isn;
+      T ws = (T)0;
+      if (isr[j] > (T)0) ws = huber_w((xi - (T)tau - zs[j]) * isr[j], delta) * isr[j] * isr[j];
+      T bb = wn * mu + ws * ((T)tau + zs[j]);
+      T cr = 0, cl = 0, cd = 0, cu = 0;
+      if (u < W - 1) {
+        const T g = gx_g[i];
+        cr = edge_weight(xi, xs[li[j] + 1], g, isgx_g[i], delta);
+        bb -= cr * g;
+      }
+      if (u > 0) {
+        const T g = gx_g[i - 1];
+        cl = edge_weight(xs[li[j] - 1], xi, g, isgx_g[i - 1], delta);
+        bb += cl * g;
+      }
+      if (v < H - 1) {
+        const T g = gy_g[i];
+        cd = edge_weight(xi, xs[li[j] + rw], g, isgy_g[i], delta);
+        bb -= cd * g;
+      }
+      if (v > 0) {
+        const T g = gy_g[i - W];
+        cu = edge_weight(xs[li[j] - rw], xi, g, isgy_g[i - W], delta);
+        bb += cu * g;
+      }
+      const T d = wn + ws + cr + cl + cd + cu;
+      dg[j] = d;
+      idg[j] = (T)1 / d;
+      cR[j] = cr; cL[j] = cl; cD[j] = cd; cU[j] = cu;
+      // r = b - A x, z = r / diag, p = z
+      const T ax = d * xi - cr * xs[li[j] + 1] - cl * xs[li[j] - 1] - cd * xs[li[j] + rw] - cu * xs[li[j] - rw];
+      const T r = bb - ax;
+      rr[j] = r;
+      const T z = r * idg[j];
+      pv[j] = z;
+      rz += (double)r * (double)z;
+      r2 += (double)r * (double)r;
+      b2 += (double)bb * (double)bb;
+    }
+    __syncthreads();   // all reads of xs done before ps is written (distinct arrays; kept for clarity)
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      if (!own[j]) continue;
+      ps[li[j]] = pv[j];
+      tm.publish(e, lxy[j] & 0xffff, lxy[j] >> 16, pv[j]);
+    }
+    vals[0] = rz; vals[1] = r2; vals[2] = b2;
+    if (!tm.sync(e++, tol_mode ? 3 : 1, vals, tot, gval, true)) return;
+#pragma unroll
+    for (int m = 0; m < GMAX; ++m)
+      if (tm.g_src[m] >= 0) ps[tm.g_li[m]] = gval[m];
+    double rz_t = tot[0];
+    const double bnorm = tol_mode ? sqrt(tot[2]) : 0.0;
+    bool converged = false;
+    if (tol_mode) {
+      relres = bnorm > 0.0 ? sqrt(tot[1]) / bnorm : 0.0;
+      converged = sqrt(tot[1]) <= a.cg_rtol * bnorm;
+    }
+    __syncthreads();
+
+    int it = 0;
+    T qv[PPT];
+    while (!converged && it < limit && rz_t != 0.0) {
+      // q = A p (5-point stencil; ghost ring holds the neighbours' p)
+      double pq = 0.0;
+#pragma unroll
+      for (int j = 0; j < PPT; ++j) {
+        qv[j] = (T)0;
+        if (!own[j]) continue;
+        const int l = li[j];
+        const T q = dg[j] * pv[j] - cR[j] * ps[l + 1] - cL[j] * ps[l - 1] - cD[j] * ps[l + rw] - cU[j] * ps[l - rw];
+        qv[j] = q;
+        pq += (double)pv[j] * (double)q;
+      }
+      vals[0] = pq;
+      if (!tm.sync(e++, 1, vals, tot, gval, false)) return;
+      const double alpha = rz_t / tot[0];
+      const T al = (T)alpha;
+      double rzn = 0.0, rrn = 0.0;
+#pragma unroll
+      for (int j = 0; j < PPT; ++j) {
+        if (!own[j]) continue;
+        xr[j] += al * pv[j];
+        rr[j] -= al * qv[j];
+        const T z = rr[j] * idg[j];
+        qv[j] = z;   // reuse as z
+        rzn += (double)rr[j] * (double)z;
+        rrn += (double)rr[j] * (double)rr[j];
+      }
+      ++it;
+      if (!tol_mode && it == limit) break;
+#pragma unroll
+      for (int j = 0; j < PPT; ++j)
+        if (own[j]) tm.publish(e, lxy[j] & 0xffff, lxy[j] >> 16, qv[j]);
+      vals[0] = rzn; vals[1] = rrn;
+      if (!tm.sync(e++, tol_mode ? 2 : 1, vals, tot, gval, true)) return;
+      if (tol_mode) {
+        relres = bnorm > 0.0 ? sqrt(tot[1]) / bnorm : 0.0;
+        if (sqrt(tot[1]) <= a.cg_rtol * bnorm) {
+          converged = true;
+          break;
+        }
+      }
+      const T be = (T)(tot[0] / rz_t);
+      rz_t = tot[0];
+#pragma unroll
+      for (int j = 0; j < PPT; ++j) {
+        if (!own[j]) continue;
+        pv[j] = fma(be, pv[j], qv[j]);
+        ps[li[j]] = pv[j];
+      }
+#pragma unroll
+      for (int m = 0; m < GMAX; ++m)
+        if (tm.g_src[m] >= 0) ps[tm.g_li[m]] = fma(be, ps[tm.g_li[m]], gval[m]);
+      __syncthreads();
+    }
+    cg_total += it;
+
+    // ---- scale step: semi weights at (x_new, tau), tau = sum w (x - z) / sum w (R13)
+    double num = 0.0, den = 0.0, cnt = 0.0;
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      if (!own[j]) continue;
+      if (isr[j] > (T)0) {
+        const T w = huber_w((xr[j] - (T)tau - zs[j]) * isr[j], delta) * isr[j] * isr[j];
+        num += (double)w * (double)(xr[j] - zs[j]);
+        den += (double)w;
+        cnt += 1.0;
+      }
+      tm.publish(e, lxy[j] & 0xffff, lxy[j] >> 16, xr[j]);
+    }
+    vals[0] = num; vals[1] = den; vals[2] = cnt;
+    if (!tm.sync(e++, 3, vals, tot, gval, true)) return;
+    if (tot[1] > 0.0) tau = tot[0] / tot[1];
+    n_valid = tot[2];
+#pragma unroll
+    for (int j = 0; j < PPT; ++j)
+      if (own[j]) xs[li[j]] = xr[j];
+#pragma unroll
+    for (int m = 0; m < GMAX; ++m)
+      if (tm.g_src[m] >= 0) xs[tm.g_li[m]] = gval[m];
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int j = 0; j < PPT; ++j)
+    if (own[j]) x_g[gi[j]] = xr[j];
+  if (b == 0 && tid == 0) {
+    a.scal->tau = tau;
+    a.scal->cg_iterations = cg_total;
+    a.scal->cg_rel_residual = relres;
+    a.scal->n_valid = (int32_t)n_valid;
+  }
+}
+
+template <typename T>
+size_t smem_for(const Tiling& t) {
+  const size_t ring = (size_t)(t.tile_h + 2) * (t.tile_w + 2);
+  return sizeof(double) * (NW * NV_MAX + NV_MAX * (size_t)t.blocks + NV_MAX + 2) + 2 * ring * sizeof(T);
+}
+
+template <typename T>
+hipError_t solve_t(const Tiling& t, const SolveArgs& a, hipStream_t s) {
+  const size_t sm = smem_for<T>(t);
+  void* args[] = {const_cast<SolveArgs*>(&a)};
+  const void* fn = nullptr;
+  switch (t.ppt) {
+#define KF_PPT(n) case n: fn = reinterpret_cast<const void*>(&k_solve<T, n>); break;
+    KF_PPT(1) KF_PPT(2) KF_PPT(3) KF_PPT(4) KF_PPT(5) KF_PPT(6) KF_PPT(8)
+#undef KF_PPT
+    default: return hipErrorInvalidValue;
+  }
+  if (sm > 48 * 1024) {
+    hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+    if (err != hipSuccess) return err;
+  }
+  return hipLaunchCooperativeKernel(fn, dim3(t.blocks), dim3(NT), args, (unsigned)sm, s);
+}
+
+}  // namespace
+
+size_t solve_smem_bytes(int prec, const Tiling& t) {
+  return prec == KF_F64 ? smem_for<double>(t) : smem_for<float>(t);
+}
+
+hipError_t launch_solve(int prec, const Tiling& t, const SolveArgs& a, hipStream_t s) {
+  if (prec == KF_F64) return solve_t<double>(t, a, s);
+  return solve_t<float>(t, a, s);
+}
+
+}  // namespace kf

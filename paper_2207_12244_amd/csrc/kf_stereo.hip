@@ -1,0 +1,413 @@
+// Semi-dense estimation (Sec. II-B): epipolar SSD search, interpolation between
+// two steps, variance of eq. (semi), inverse-depth Gaussian filter.
+//
+// Work mapping: a group of G = min(N_s, 64) lanes of one wavefront handles one
+// textured keyframe pixel; lane l evaluates samples k = l, l + G, ... The
+// keyframe pattern (5 or 25 values) is staged once per pixel in LDS and read
+// by every lane as a broadcast; the argmin over the N_s SSDs is a butterfly of
+// cross-lane shuffles inside the group with ties resolved to the smaller k.
+#include "kf_internal.h"
+
+namespace kf {
+
+namespace {
+
+constexpr int ST_THREADS = 256;
+constexpr int ST_WAVES = ST_THREADS / 64;
+
+template <typename T>
+struct PixelGeom {
+  T A0, A1, A2;      // H (u, v, 1)
+  T cx, cy;          // segment centre in image 1
+  T lx, ly;          // unit direction of the segment (image 1)
+  T h;               // step between samples (>= 1 px)
+  T l0x, l0y;        // keyframe epipolar direction (LINE5)
+  bool use_x;        // solve rho from the x coordinate
+  bool ok;
+};
+
+// Bilinear intensity of the uint8 new frame at (u, v), 0 <= u <= W-1, 0 <= v <= H-1.
+template <typename T>
+__device__ inline T bilin_u8(const uint8_t* img, int W, int H, T u, T v) {
+  T fu = floor(u), fv = floor(v);
+  fu = fu < (T)(W - 2) ? fu : (T)(W - 2);
+  fv = fv < (T)(H - 2) ? fv : (T)(H - 2);
+  fu = fu > (T)0 ? fu : (T)0;
+  fv = fv > (T)0 ? fv : (T)0;
+  const T f = u - fu, g = v - fv;
+  const size_t i = (size_t)(int)fv * W + (int)fu;
+  const T i00 = (T)img[i], i10 = (T)img[i + 1], i01 = (T)img[i + W], i11 = (T)img[i + W + 1];
+  const T top = i00 + f * (i10 - i00);
+  const T bot = i01 + f * (i11 - i01);
+  return top + g * (bot - top);
+}
+
+// Same for the resident keyframe image (storage type TI).
+template <typename T, typename TI>
+__device__ inline T bilin_kf(const TI* img, int W, int H, T u, T v) {
+  T fu = floor(u), fv = floor(v);
+  fu = fu < (T)(W - 2) ? fu : (T)(W - 2);
+  fv = fv < (T)(H - 2) ? fv : (T)(H - 2);
+  fu = fu > (T)0 ? fu : (T)0;
+  fv = fv > (T)0 ? fv : (T)0;
+  const T f = u - fu, g = v - fv;
+  const size_t i = (size_t)(int)fv * W + (int)fu;
+  const T i00 = load_img<TI, T>(img, i), i10 = load_img<TI, T>(img, i + 1);
+  const T i01 = load_img<TI, T>(img, i + W), i11 = load_img<TI, T>(img, i + W + 1);
+  const T top = i00 + f * (i10 - i00);
+  const T bot = i01 + f * (i11 - i01);
+  return top + g * (bot - top);
+}
+
+template <typename T>
+__device__ inline bool inside(T u, T v, int W, int H) {
+  return u >= (T)0 && u <= (T)(W - 1) && v >= (T)0 && v <= (T)(H - 1);
+}
+
+// Epipolar geometry of one pixel (identical in every lane of its group).
+template <typename T, int PAT, int NS>
+__device__ inline PixelGeom<T> pixel_geometry(const StereoArgs& a, T u, T v, T rho, T var, bool has) {
+  const FrameConst& c = a.fc;
+  PixelGeom<T> g;
+  const T H0 = (T)c.Hm[0], H1 = (T)c.Hm[1], H2 = (T)c.Hm[2];
+  const T H3 = (T)c.Hm[3], H4 = (T)c.Hm[4], H5 = (T)c.Hm[5];
+  const T H6 = (T)c.Hm[6], H7 = (T)c.Hm[7], H8 = (T)c.Hm[8];
+  const T b0 = (T)c.b[0], b1 = (T)c.b[1], b2 = (T)c.b[2];
+  const T rmin = (T)c.rho_min, rmax = (T)c.rho_max;
+  g.A0 = H0 * u + H1 * v + H2;
+  g.A1 = H3 * u + H4 * v + H5;
+  g.A2 = H6 * u + H7 * v + H8;
+  // search interval in inverse depth: rho +- 2 sigma clamped, or the whole range
+  T lo = rmin, hi = rmax;
+  if (has) {
+    const T sd = sqrt(var);
+    lo = rho - (T)2 * sd;
+    lo = lo > rmin ? lo : rmin;
+    hi = rho + (T)2 * sd;
+    hi = hi < rmax ? hi : rmax;
+  }
+  g.ok = hi > lo;
+  const T dlo = g.A2 + lo * b2, dhi = g.A2 + hi * b2;
+  g.ok = g.ok && dlo > (T)0 && dhi > (T)0;
+  const T plx = (g.A0 + lo * b0) / dlo, ply = (g.A1 + lo * b1) / dlo;
+  const T phx = (g.A0 + hi * b0) / dhi, phy = (g.A1 + hi * b1) / dhi;
+  const T dx = phx - plx, dy = phy - ply;
+  const T L = sqrt(dx * dx + dy * dy);
+  g.ok = g.ok && isfinite((double)L) && L >= (T)1e-6;
+  g.lx = g.ok ? dx / L : (T)1;
+  g.ly = g.ok ? dy / L : (T)0;
+  const T hs = L / (T)(NS - 1);
+  g.h = g.ok ? (hs > (T)1 ? hs : (T)1) : (T)1;
+  g.cx = g.ok ? (plx + phx) / (T)2 : u;
+  g.cy = g.ok ? (ply + phy) / (T)2 : v;
+  g.use_x = fabs((double)g.lx) >= fabs((double)g.ly);
+  g.l0x = (T)0;
+  g.l0y = (T)0;
+  if (PAT == KF_PAT_LINE5) {
+    // keyframe epipolar line through the pixel and the epipole K c1
+    const T ex = (T)c.e0[0], ey = (T)c.e0[1], ez = (T)c.e0[2];
+    const T ddx = ez * u - ex, ddy = ez * v - ey;
+    const T n0 = sqrt(ddx * ddx + ddy * ddy);
+    const bool ok0 = n0 > (T)0 && isfinite((double)n0);
+    T l0x = ok0 ? ddx / n0 : (T)0, l0y = ok0 ? ddy / n0 : (T)0;
+    // orient it so that a step along it moves the projection along +l1
+    const T rc = (lo + hi) / (T)2;
+    const T q0d = g.A2 + rc * b2;
+    const T q0x = (g.A0 + rc * b0) / q0d, q0y = (g.A1 + rc * b1) / q0d;
+    const T u1 = u + l0x, v1 = v + l0y;
+    const T B0 = H0 * u1 + H1 * v1 + H2 + rc * b0;
+    const T B1 = H3 * u1 + H4 * v1 + H5 + rc * b1;
+    const T B2 = H6 * u1 + H7 * v1 + H8 + rc * b2;
+    const T q1x = B0 / B2, q1y = B1 / B2;
+    if ((q1x - q0x) * g.lx + (q1y - q0y) * g.ly < (T)0) {
+      l0x = -l0x;
+      l0y = -l0y;
+    }
+    g.ok = g.ok && ok0 && isfinite((double)l0x) && isfinite((double)l0y);
+    g.l0x = l0x;
+    g.l0y = l0y;
+  }
+  return g;
+}
+
+// Position and inverse depth of sample k.
+template <typename T, int NS>
+__device__ inline void sample_pos(const PixelGeom<T>& g, const FrameConst& c, int k, T& px, T& py, T& rk) {
+  const T off = (T)k - (T)((NS - 1) * 0.5);
+  px = g.cx + off * g.h * g.lx;
+  py = g.cy + off * g.h * g.ly;
+  const T pm = g.use_x ? px : py;
+  const T Am = g.use_x ? g.A0 : g.A1;
+  const T bm = g.use_x ? (T)c.b[0] : (T)c.b[1];
+  rk = (pm * g.A2 - Am) / (bm - pm * (T)c.b[2]);
+}
+
+// Photometric residual of pattern point j at sample position (px, py).
+template <typename T, int PAT>
+__device__ inline T point_residual(const StereoArgs& a, const PixelGeom<T>& g, T px, T py, int j, T pat_j) {
+  T tu, tv;
+  if (PAT == KF_PAT_LINE5) {
+    const T jj = (T)(j - 2);
+    tu = px + jj * g.lx;
+    tv = py + jj * g.ly;
+  } else {
+    tu = px + (T)(j % 5 - 2);
+    tv = py + (T)(j / 5 - 2);
+  }
+  return bilin_u8<T>(a.i1, a.W, a.H, tu, tv) - pat_j;
+}
+
+template <typename T>
+__device__ inline T shfl_xor_t(T v, int m) { return __shfl_xor(v, m, 64); }
+template <typename T>
+__device__ inline T shfl_t(T v, int src) { return __shfl(v, src, 64); }
+
+template <typename T, typename TI, int PAT, int NS>
+__global__ __launch_bounds__(ST_THREADS) void k_stereo(StereoArgs a) {
+  constexpr int G = NS < 64 ? NS : 64;    // lanes per pixel
+  constexpr int S = NS / G;                // samples per lane
+  constexpr int GPW = 64 / G;              // pixels per wavefront
+  constexpr int P = PAT == KF_PAT_LINE5 ? 5 : 25;
+  constexpr T INF = (T)INFINITY;
+
+  __shared__ TI pat_lds[ST_WAVES][GPW][P];
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int grp = lane / G;
+  const int gl = lane % G;
+  const int count = a.scal_ro->mask_count;
+  const int groups_per_block = ST_WAVES * GPW;
+  const int ngroups = gridDim.x * groups_per_block;
+  const int my_group = blockIdx.x * groups_per_block + wave * GPW + grp;
+  const int rounds = (count + ngroups - 1) / ngroups;
+  const TI* i0 = static_cast<const TI*>(a.i0);
+  T* rho_s = static_cast<T*>(a.rho);
+  T* var_s = static_cast<T*>(a.var);
+  const int W = a.W, H = a.H;
+  int updated_here = 0;
+
+  for (int r = 0; r < rounds; ++r) {      // block-uniform trip count (LDS barriers below)
+    const int idx = my_group + r * ngroups;
+    const bool active = idx < count;
+    const int pix = active ? a.list[idx] : 0;
+    const T u = (T)(pix % W), v = (T)(pix / W);
+    const T rho0 = rho_s[pix], var0 = var_s[pix];
+    const bool has = var0 > (T)0;
+    PixelGeom<T> g = pixel_geometry<T, PAT, NS>(a, u, v, rho0, var0, has);
+    g.ok = g.ok && active;
+
+    // stage the keyframe pattern I0(a_j) in LDS
+    // (textured pixels lie >= 2 px inside the image, so every point is in bounds)
+    for (int j = gl; j < P; j += G) {
+      T val = (T)0;
+      if (active) {
+        if (PAT == KF_PAT_LINE5) {
+          const T jj = (T)(j - 2);
+          val = bilin_kf<T, TI>(i0, W, H, u + jj * g.l0x, v + jj * g.l0y);
+        } else {
+          const int iu = (int)u + (j % 5 - 2), iv = (int)v + (j / 5 - 2);
+          val = load_img<TI, T>(i0, (size_t)iv * W + iu);
+        }
+      }
+      pat_lds[wave][grp][j] = to_img<TI, T>(val);
+    }
+    __syncthreads();
+    T pat[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) pat[j] = load_img<TI, T>(&pat_lds[wave][grp][0], j);
+
+    // SSD of this lane's samples
+    T ssd[S];
+    T best = INF;
+    int bestk = 0x7fffffff;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int k = gl + G * s;
+      T px, py, rk;
+      sample_pos<T, NS>(g, a.fc, k, px, py, rk);
+      bool ok = g.ok && isfinite((double)rk) && rk >= (T)a.fc.rho_min && rk <= (T)a.fc.rho_max;
+      T acc = (T)0;
+      if (PAT == KF_PAT_LINE5) {
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+          const T jj = (T)(j - 2);
+          ok = ok && inside<T>(px + jj * g.lx, py + jj * g.ly, W, H);
+        }
+        if (ok) {
+#pragma unroll
+          for (int j = 0; j < 5; ++j) {
+            const T e = point_residual<T, PAT>(a, g, px, py, j, pat[j]);
+            acc += e * e;
+          }
+        }
+      } else {
+        ok = ok && px - (T)2 >= (T)0 && px + (T)2 <= (T)(W - 1) && py - (T)2 >= (T)0 &&
+             py + (T)2 <= (T)(H - 1);
+        if (ok) {
+          // 6 x 6 tap window shared by the 25 points (translation-only warp)
+          const T fpx = floor(px), fpy = floor(py);
+          const T f = px - fpx, gg = py - fpy;
+          const int c0 = (int)fpx - 2, r0 = (int)fpy - 2;
+          T hprev[5];
+#pragma unroll
+          for (int n = 0; n < 6; ++n) {
+            int rr = r0 + n;
+            rr = rr < H - 1 ? rr : H - 1;
+            const uint8_t* row = a.i1 + (size_t)rr * W;
+            T t[6];
+#pragma unroll
+            for (int m = 0; m < 6; ++m) {
+              int cc = c0 + m;
+              cc = cc < W - 1 ? cc : W - 1;
+              t[m] = (T)row[cc];
+            }
+            T hrow[5];
+#pragma unroll
+            for (int m = 0; m < 5; ++m) hrow[m] = t[m] + f * (t[m + 1] - t[m]);
+            if (n > 0) {
+#pragma unroll
+              for (int m = 0; m < 5; ++m) {
+                const T val = hprev[m] + gg * (hrow[m] - hprev[m]);
+                const T e = val - pat[(n - 1) * 5 + m];
+                acc += e * e;
+              }
+            }
+#pragma unroll
+            for (int m = 0; m < 5; ++m) hprev[m] = hrow[m];
+          }
+        }
+      }
+      ssd[s] = ok ? acc : INF;
+      if (ssd[s] < best) {          // s increases with k: keeps the first minimum
+        best = ssd[s];
+        bestk = k;
+      }
+    }
+    // argmin across the group: smaller SSD, ties -> smaller k
+#pragma unroll
+    for (int m = 1; m < G; m <<= 1) {
+      const T ob = shfl_xor_t(best, m);
+      const int ok_ = __shfl_xor(bestk, m, 64);
+      if (ob < best || (ob == best && ok_ < bestk)) {
+        best = ob;
+        bestk = ok_;
+      }
+    }
+    const bool any_valid = g.ok && best < INF;
+    const int kstar = bestk;
+    // SSD of the two neighbours k* - 1 and k* + 1
+    T s_m = INF, s_p = INF;
+    {
+      const int km = any_valid ? kstar - 1 : -1;
+      const int kp = any_valid ? kstar + 1 : NS;
+      const int base = grp * G;
+      T vm = INF, vp = INF;
+      // every lane reads its own slot value for the owner's sample index
+      const int slot_m = km >= 0 ? km / G : 0, slot_p = kp < NS ? kp / G : 0;
+      T mine_m = ssd[0], mine_p = ssd[0];
+#pragma unroll
+      for (int s = 1; s < S; ++s) {
+        if (slot_m == s) mine_m = ssd[s];
+        if (slot_p == s) mine_p = ssd[s];
+      }
+      vm = shfl_t(mine_m, base + (km >= 0 ? km % G : 0));
+      vp = shfl_t(mine_p, base + (kp < NS ? kp % G : 0));
+      s_m = km >= 0 ? vm : INF;
+      s_p = kp < NS ? vp : INF;
+    }
+    const bool has_nb = any_valid && (s_m < INF || s_p < INF);
+    const int nstar = (s_m <= s_p) ? kstar - 1 : kstar + 1;
+
+    // residual vectors at k* and n*: lane j of the group computes point j
+    T pxk = 0, pyk = 0, rk_k = 0, pxn = 0, pyn = 0, rk_n = 0;
+    if (has_nb) {
+      sample_pos<T, NS>(g, a.fc, kstar, pxk, pyk, rk_k);
+      sample_pos<T, NS>(g, a.fc, nstar, pxn, pyn, rk_n);
+    }
+    T sum_kd = 0, sum_dd = 0;
+    if (has_nb) {
+      for (int j = gl; j < P; j += G) {
+        const T pj = load_img<TI, T>(&pat_lds[wave][grp][0], j);
+        const T ek = point_residual<T, PAT>(a, g, pxk, pyk, j, pj);
+        const T en = point_residual<T, PAT>(a, g, pxn, pyn, j, pj);
+        const T de = en - ek;
+        sum_kd += ek * de;
+        sum_dd += de * de;
+      }
+    }
+#pragma unroll
+    for (int m = 1; m < G; m <<= 1) {
+      sum_kd += shfl_xor_t(sum_kd, m);
+      sum_dd += shfl_xor_t(sum_dd, m);
+    }
+    if (gl == 0 && active) {
+      a.match[pix] = (g.ok && best < INF) ? kstar : -1;
+      if (has_nb && sum_dd > (T)0) {
+        T lam = -sum_kd / sum_dd;
+        lam = lam < (T)0 ? (T)0 : (lam > (T)1 ? (T)1 : lam);
+        const T d_a = (T)1 / rk_k, d_b = (T)1 / rk_n;
+        const T dd = d_b - d_a;
+        const T dstar = d_a + lam * dd;
+        const T sp = (T)a.fc.sigma_photo;
+        const T var_d = sp * sp * dd * dd / sum_dd;       // eq. (semi) with J = de / dd
+        const T ro = (T)1 / dstar;
+        const T d2 = dstar * dstar;
+        const T vo = var_d / (d2 * d2);
+        if (isfinite((double)var_d) && var_d > (T)0 && isfinite((double)dstar) && dstar > (T)0 &&
+            isfinite((double)vo) && vo > (T)0) {
+          if (has) {   // Gaussian product with the current estimate
+            rho_s[pix] = (vo * rho0 + var0 * ro) / (var0 + vo);
+            var_s[pix] = var0 * vo / (var0 + vo);
+          } else {
+            rho_s[pix] = ro;
+            var_s[pix] = vo;
+          }
+          ++updated_here;
+        }
+      }
+    }
+    __syncthreads();   // LDS pattern slot reused next round
+  }
+  // one atomic per wavefront
+  for (int m = 32; m > 0; m >>= 1) updated_here += __shfl_xor(updated_here, m, 64);
+  if (lane == 0 && updated_here) atomicAdd(&a.scal->n_updated, updated_here);
+}
+
+template <typename T, typename TI, int PAT>
+hipError_t stereo_ns(int ns, const StereoArgs& a, int blocks, hipStream_t s) {
+  switch (ns) {
+#define KF_NS(n) case n: hipLaunchKernelGGL((k_stereo<T, TI, PAT, n>), dim3(blocks), dim3(ST_THREADS), 0, s, a); break;
+    KF_NS(4) KF_NS(8) KF_NS(16) KF_NS(32) KF_NS(64) KF_NS(128) KF_NS(256) KF_NS(512) KF_NS(1024)
+#undef KF_NS
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int PREC>
+hipError_t stereo_prec(int pattern, int ns, const StereoArgs& a, int blocks, hipStream_t s) {
+  using T = typename Form<PREC>::T;
+  using TI = typename Form<PREC>::TI;
+  if (pattern == KF_PAT_LINE5) return stereo_ns<T, TI, KF_PAT_LINE5>(ns, a, blocks, s);
+  return stereo_ns<T, TI, KF_PAT_SQ5X5>(ns, a, blocks, s);
+}
+
+}  // namespace
+
+int stereo_grid_blocks(int device) {
+  int cus = 256;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) cus = 256;
+  return cus * 8;
+}
+
+hipError_t launch_stereo(int prec, int pattern, int ns, const StereoArgs& a, int blocks, hipStream_t s) {
+  switch (prec) {
+    case KF_F64: return stereo_prec<KF_F64>(pattern, ns, a, blocks, s);
+    case KF_F32: return stereo_prec<KF_F32>(pattern, ns, a, blocks, s);
+    case KF_BF16_F32: return stereo_prec<KF_BF16_F32>(pattern, ns, a, blocks, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace kf

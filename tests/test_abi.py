@@ -1,0 +1,109 @@
+"""C ABI checks that need no GPU: the library loads, exports every declared symbol,
+and rejects bad arguments on the host before touching a device."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "kf.h")
+
+
+def _lib():
+    from paper_2207_12244_amd import kf
+    if not os.path.exists(kf.LIB_PATH):
+        pytest.skip("libkf.so not built (run __graft_entry__.build())")
+    return kf, kf.load_library()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(kf_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    kf, lib = _lib()
+    names = declared_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(kf.EXPORTED_SYMBOLS)
+
+
+def test_defaults_follow_the_documented_readings():
+    kf, lib = _lib()
+    cfg = kf.kf_config_default(640, 480)
+    assert (cfg.width, cfg.height) == (640, 480)
+    assert cfg.fx == cfg.fy == 512.0 and cfg.cx == 320.0 and cfg.cy == 240.0
+    assert cfg.n_gn == 10 and cfg.n_samples == 32 and cfg.pattern == kf.KF_PAT_LINE5
+    assert cfg.huber_delta == 1.345 and cfg.d_near == 0.4 and cfg.d_far == 10.0
+    assert cfg.grad_gate == 6.0 and cfg.sigma_photo == 1.0 and cfg.r_floor == 1e-6
+
+
+@pytest.mark.parametrize("field,value", [
+    ("width", 4), ("height", 9000), ("n_samples", 48), ("n_samples", 2048), ("pattern", 7), ("n_gn", 0),
+    ("n_cg", 0), ("cg_rtol", -1.0), ("huber_delta", 0.0), ("d_near", 20.0), ("sigma_photo", 0.0),
+    ("r_floor", 0.0), ("precision", 9), ("fx", float("nan")),
+])
+def test_invalid_config_rejected(field, value):
+    kf, lib = _lib()
+    cfg = kf.kf_config_default(160, 120)
+    setattr(cfg, field, value)
+    assert kf.kf_workspace_bytes(cfg) == 0
+    h = ctypes.c_void_p()
+    assert lib.kf_create(ctypes.byref(cfg), ctypes.byref(h)) == kf.KF_ERR_ARG
+    assert not h.value
+
+
+def test_workspace_size_and_oom():
+    kf, lib = _lib()
+    cfg = kf.kf_config_default(160, 120)
+    n = kf.kf_workspace_bytes(cfg)
+    assert n > 160 * 120 * 4 * 10
+    cfg.workspace = ctypes.c_void_p(1 << 20)     # never dereferenced by kf_create
+    cfg.workspace_bytes = n - 1
+    h = ctypes.c_void_p()
+    assert lib.kf_create(ctypes.byref(cfg), ctypes.byref(h)) == kf.KF_ERR_OOM
+    cfg.workspace_bytes = n
+    cfg.workspace = None
+    assert lib.kf_create(ctypes.byref(cfg), ctypes.byref(h)) == kf.KF_ERR_ARG
+    f64 = kf.kf_config_default(160, 120)
+    f64.precision = kf.KF_F64
+    assert kf.kf_workspace_bytes(f64) > n
+
+
+def test_calls_out_of_order_and_null_arguments():
+    kf, lib = _lib()
+    cfg = kf.kf_config_default(64, 48)
+    cfg.workspace = ctypes.c_void_p(1 << 20)
+    cfg.workspace_bytes = kf.kf_workspace_bytes(cfg)
+    h = kf.kf_create(cfg)
+    try:
+        pose = kf._pose([[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 1, 0], [0, 0, 0, 1]])
+        assert lib.kf_fuse_frame(h, ctypes.c_void_p(4096), pose) == kf.KF_ERR_STATE
+        assert lib.kf_solve(h) == kf.KF_ERR_STATE
+        assert lib.kf_read_depth(h, None, None, None) == kf.KF_ERR_STATE
+        assert b"before kf_set_prior" in lib.kf_last_error(h)
+        assert lib.kf_set_prior(h, None, None, None, None, None, None, None, pose) == kf.KF_ERR_ARG
+        bad = kf._pose([[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 1, 0], [0, 0, 1, 1]])
+        p = ctypes.c_void_p(4096)
+        assert lib.kf_set_prior(h, p, p, p, p, p, p, p, bad) == kf.KF_ERR_ARG
+    finally:
+        kf.kf_destroy(h)
+    assert lib.kf_create(None, None) == kf.KF_ERR_ARG
+    assert lib.kf_last_error(None) == b"no context"
+    assert lib.kf_status_string(kf.KF_ERR_TIMEOUT) == b"KF_ERR_TIMEOUT"
+
+
+def test_manual_tiling_validated():
+    kf, lib = _lib()
+    cfg = kf.kf_config_default(160, 120)
+    cfg.solver_tiles_x, cfg.solver_tiles_y = 7, 5
+    assert kf.kf_workspace_bytes(cfg) > 0
+    cfg.solver_tiles_x, cfg.solver_tiles_y = 7, 0
+    assert kf.kf_workspace_bytes(cfg) == 0
+    cfg.solver_tiles_x, cfg.solver_tiles_y = 1, 1      # 19200 px in one workgroup: too many per thread
+    assert kf.kf_workspace_bytes(cfg) == 0

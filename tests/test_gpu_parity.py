@@ -1,0 +1,261 @@
+"""GPU (gfx950) vs FP64 oracle, stage by stage and end to end, through the C ABI."""
+
+import numpy as np
+import pytest
+
+import kfsynth
+from oracle import fusion, stereo
+from oracle.fusion import SolverParams
+from oracle.stereo import StereoParams, UPDATED
+
+import gpu_util as gu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def c0():
+    return kfsynth.config_case(0, 0)
+
+
+@pytest.fixture(scope="module")
+def c1_short():
+    return kfsynth.config_case(1, 0, frames=2)
+
+
+# ------------------------------------------------------------------ keyframe init
+
+@pytest.mark.parametrize("precision", ["f64", "f32", "bf16"])
+def test_prior_init_mask_and_state(c0, precision):
+    gu.say(f"[prior-init] config 0 case 0 {precision}")
+    kf = gu.make_gpu_kf(c0, precision, "line5", 32)
+    st = kf.export_state()
+    match = st["match"].cpu().numpy()
+    mask = stereo.texture_mask(c0.image0)
+    assert np.array_equal(match == -1, mask)                 # texture gate: bit-exact
+    assert np.all((match == -1) | (match == -2))
+    dt = gu.np_map_dtype(precision)
+    assert np.array_equal(st["x"].cpu().numpy(), c0.priors.logdepth.astype(dt))
+    assert not st["rho"].cpu().numpy().any() and not st["var"].cpu().numpy().any()
+    assert st["tau"] == 0.0
+    assert kf.stats().n_searched == int(mask.sum())
+
+
+# ------------------------------------------------------------------ stereo stage
+
+def _compare_search(res, st, margin_eps, rel_tol, label):
+    """Index parity outside the near-tie band, value parity where the index agrees."""
+    match = st["match"].cpu().numpy().ravel()[res.pix]
+    rho = st["rho"].cpu().numpy().astype(np.float64).ravel()[res.pix]
+    var = st["var"].cpu().numpy().astype(np.float64).ravel()[res.pix]
+    has = res.k_best >= 0
+    s = np.sort(np.where(np.isfinite(res.ssd), res.ssd, np.inf), axis=1)
+    best = s[:, 0]
+    with np.errstate(invalid="ignore"):
+        margin = np.where(np.isfinite(s[:, 1]), s[:, 1] - s[:, 0], np.inf)
+    clear = has & (margin >= margin_eps(best))
+    gu.say(f"[{label}] searched {res.pix.size} with-index {has.sum()} clear {clear.sum()} "
+           f"tie-band {(has & ~clear).sum()}")
+    mism_clear = np.count_nonzero(match[clear] != res.k_best[clear])
+    assert mism_clear == 0, f"{mism_clear} index mismatches outside the tie band"
+    # inside the band the GPU's choice must be one of the near-best samples
+    band = np.flatnonzero(has & ~clear)
+    for r in band:
+        k = match[r]
+        assert k >= 0 and res.ssd[r, k] <= best[r] + margin_eps(best[r]), (r, k)
+    assert np.array_equal(match[~has], np.full((~has).sum(), -1))
+    upd = (res.status == UPDATED) & (match == res.k_best)
+    gpu_upd = var > 0
+    same = upd & gpu_upd
+    assert np.count_nonzero(upd & ~gpu_upd) == 0 and np.count_nonzero(gpu_upd & (res.status != UPDATED)) == 0
+    er = np.abs(rho[same] / res.rho_obs[same] - 1)
+    ev = np.abs(var[same] / res.var_obs[same] - 1)
+    gu.say(f"[{label}] updated {same.sum()} rho rel max {er.max():.3e} rms {np.sqrt(np.mean(er**2)):.3e} "
+           f"var rel max {ev.max():.3e}")
+    assert er.max() <= rel_tol[0] and ev.max() <= rel_tol[1]
+    return same
+
+
+def test_stereo_first_frame_f64_line5(c0):
+    gu.say("[stereo] config 0 case 0 f64 line5 N_s=32")
+    kf = gu.make_gpu_kf(c0, "f64", "line5", 32)
+    t = gu.torch()
+    kf.stereo_update(gu.dev(c0.images[0], t.uint8), c0.poses[0])
+    st = kf.export_state()
+    res = gu.first_frame_search(c0, "line5", 32)
+    _compare_search(res, st, lambda b: 1e-9 * (1 + b), (1e-10, 1e-9), "stereo-f64")
+    assert kf.stats().n_updated == int(np.sum(res.status == UPDATED))
+
+
+@pytest.mark.parametrize("precision", ["f32", "bf16"])
+def test_stereo_first_frame_sq5x5_float(c1_short, precision):
+    """float32 kernels: indices decided in float32 on both sides (R18 band), values vs FP64."""
+    c = c1_short
+    gu.say(f"[stereo] config 1 case 0 {precision} sq5x5 N_s=64")
+    kf = gu.make_gpu_kf(c, precision, "sq5x5", 64)
+    t = gu.torch()
+    kf.stereo_update(gu.dev(c.images[0], t.uint8), c.poses[0])
+    st = kf.export_state()
+    res32 = gu.first_frame_search(c, "sq5x5", 64, dtype=np.float32)
+    P = 25
+    same = _compare_search(res32, st, lambda b: 1e-3 * (1 + b) + 0.05 * P, (2e-3, 2e-2), f"stereo-{precision}")
+    res64 = gu.first_frame_search(c, "sq5x5", 64)
+    rho = st["rho"].cpu().numpy().astype(np.float64).ravel()[res64.pix]
+    both = same & (res64.status == UPDATED) & (res64.k_best == res32.k_best)
+    e64 = np.abs(rho[both] / res64.rho_obs[both] - 1)
+    gu.say(f"[stereo-{precision}] vs FP64 oracle: rho rel max {e64.max():.3e} rms {np.sqrt(np.mean(e64**2)):.3e}")
+
+
+# ------------------------------------------------------------------ solver stage
+
+def _oracle_state(case):
+    """FP64 oracle filter state after the first frame (the input both solvers get)."""
+    sp = StereoParams(n_samples=32, pattern="line5")
+    mask = stereo.texture_mask(case.image0)
+    z = np.zeros((case.H, case.W))
+    r, v, ok, _ = stereo.stereo_update(case.image0, case.images[0], case.K, case.T_wc0, case.poses[0], z, z,
+                                       np.zeros((case.H, case.W), bool), mask, sp)
+    return np.where(ok, r, 0.0), np.where(ok, v, 0.0)
+
+
+@pytest.mark.parametrize("precision,mode", [("f64", "rtol"), ("f64", "fixed"), ("f32", "fixed"),
+                                            ("bf16", "fixed")])
+def test_solver_parity(c0, precision, mode):
+    gu.say(f"[solver] config 0 case 0 {precision} {mode}")
+    rho, var = _oracle_state(c0)
+    dt = gu.np_map_dtype(precision)
+    rho_in, var_in = rho.astype(dt), var.astype(dt)
+    if mode == "rtol":
+        kf = gu.make_gpu_kf(c0, precision, "line5", 32, n_gn=10, cg_rtol=1e-12, cg_max=4000)
+        prm = SolverParams(n_gn=10, cg_rtol=1e-12, cg_max=4000, linear_solver="pcg")
+    else:
+        kf = gu.make_gpu_kf(c0, precision, "line5", 32, n_gn=10, n_cg=20)
+        prm = SolverParams(n_gn=10, n_cg=20, linear_solver="pcg")
+    t = gu.torch()
+    mdt = gu.map_dtype(precision)
+    kf.import_state(rho=gu.dev(rho_in, mdt), var=gu.dev(var_in, mdt))
+    kf.solve()
+    st = kf.export_state()
+    x_gpu = st["x"].cpu().numpy().astype(np.float64)
+    prior = gu.rounded_priors(c0, precision)
+    semi = gu.oracle_semi(rho_in.astype(np.float64), var_in.astype(np.float64))
+    x_o, tau_o, info = fusion.gauss_newton(prior.mu, 0.0, prior, semi, prm)
+    err = np.abs(x_gpu - x_o)
+    s = kf.stats()
+    gu.say(f"[solver-{precision}-{mode}] max|dx| {err.max():.3e} rms {np.sqrt(np.mean(err**2)):.3e} "
+           f"dtau {abs(st['tau'] - tau_o):.3e} cg_its {s.cg_iterations} relres {s.cg_rel_residual:.2e} "
+           f"n_valid {s.n_valid} (oracle {int(semi.valid.sum())})")
+    assert s.n_valid == int(semi.valid.sum())
+    if precision == "f64":
+        assert err.max() <= 1e-10 and abs(st["tau"] - tau_o) <= 1e-10
+        if mode == "rtol":
+            # same stopping rule -> same iteration count; the distance to the direct
+            # solve is the configured truncation (the oracle's own PCG shows it too)
+            assert s.cg_iterations == sum(info.cg_iterations)
+            x_d, tau_d, _ = fusion.gauss_newton(prior.mu, 0.0, prior, semi,
+                                                SolverParams(n_gn=10, linear_solver="direct"))
+            e_d = np.abs(x_gpu - x_d).max()
+            gu.say(f"[solver-f64-rtol] vs direct solves: max|dx| {e_d:.3e}")
+            assert e_d <= 5e-9
+    else:
+        assert err.max() <= 2e-4 and np.sqrt(np.mean(err ** 2)) <= 2e-5 and abs(st["tau"] - tau_o) <= 2e-5
+
+
+def test_solver_ragged_tiles(c0):
+    """Explicit 7 x 5 tiling of 160 x 120 (ragged last column / row of tiles)."""
+    gu.say("[solver] config 0 case 0 f64 fixed tiles 7x5")
+    rho, var = _oracle_state(c0)
+    kf = gu.make_gpu_kf(c0, "f64", "line5", 32, n_gn=3, n_cg=15, tiles=(7, 5))
+    t = gu.torch()
+    kf.import_state(rho=gu.dev(rho, t.float64), var=gu.dev(var, t.float64))
+    kf.solve()
+    st = kf.export_state()
+    prior = gu.rounded_priors(c0, "f64")
+    x_o, tau_o, _ = fusion.gauss_newton(prior.mu, 0.0, prior, gu.oracle_semi(rho, var),
+                                        SolverParams(n_gn=3, n_cg=15, linear_solver="pcg"))
+    err = np.abs(st["x"].cpu().numpy() - x_o)
+    gu.say(f"[solver-ragged] max|dx| {err.max():.3e} dtau {abs(st['tau'] - tau_o):.3e}")
+    assert err.max() <= 1e-10 and abs(st["tau"] - tau_o) <= 1e-10
+
+
+def test_prior_only_returns_prior_gpu():
+    """P1 on the GPU: texture-free keyframe (S empty) and g = forward difference of mu."""
+    case = kfsynth.make_case(77, 96, 64, 1)
+    mu = case.priors.logdepth
+    gx = np.zeros_like(mu)
+    gx[:, :-1] = mu[:, 1:] - mu[:, :-1]
+    gy = np.zeros_like(mu)
+    gy[:-1, :] = mu[1:, :] - mu[:-1, :]
+    maps = (mu, case.priors.logdepth_var, gx, case.priors.gx_var, gy, case.priors.gy_var)
+    flat = case.image0.copy()
+    flat[:] = 128
+    case.image0 = flat
+    for precision, tol in (("f64", 1e-12), ("f32", 2e-6)):
+        gu.say(f"[prior-only] 96x64 {precision}")
+        kf = gu.make_gpu_kf(case, precision, "line5", 32, priors=maps)
+        t = gu.torch()
+        kf.fuse_frame(gu.dev(case.images[0], t.uint8), case.poses[0])
+        d, s = kf.read_depth()
+        st = kf.stats()
+        assert st.n_searched == 0 and st.n_valid == 0
+        x = np.log(d.cpu().numpy().astype(np.float64))
+        gu.say(f"[prior-only-{precision}] max|x-mu| {np.abs(x - mu).max():.3e} scale {s}")
+        assert np.abs(x - mu.astype(gu.np_map_dtype(precision))).max() <= tol and s == 1.0
+
+
+def test_pure_rotation_produces_no_measurement(c0):
+    gu.say("[rotation] config 0 case 0 f32, zero translation")
+    T = c0.poses[0].copy()
+    T[:3, 3] = 0.0
+    kf = gu.make_gpu_kf(c0, "f32", "line5", 32)
+    t = gu.torch()
+    kf.stereo_update(gu.dev(c0.images[0], t.uint8), T)
+    st = kf.export_state()
+    assert not st["var"].cpu().numpy().any()
+    assert kf.stats().n_updated == 0
+
+
+@pytest.mark.parametrize("bad", ["nan_mu", "zero_var", "neg_gvar"])
+def test_invalid_prior_reported(c0, bad):
+    from paper_2207_12244_amd.kf import KfError, KF_ERR_INPUT
+    gu.say(f"[input-error] {bad}")
+    mu, vn, gx, vgx, gy, vgy = [m.copy() for m in c0.priors.maps()]
+    if bad == "nan_mu":
+        mu[5, 7] = np.nan
+    elif bad == "zero_var":
+        vn[3, 3] = 0.0
+    else:
+        vgx[9, 9] = -1.0
+    kf = gu.make_gpu_kf(c0, "f32", "line5", 32, priors=(mu, vn, gx, vgx, gy, vgy))
+    with pytest.raises(KfError) as ei:
+        kf.read_depth()
+    assert ei.value.status == KF_ERR_INPUT
+
+
+# ------------------------------------------------------------------ end to end
+
+def test_end_to_end_config0(c0):
+    """Plain FP64 form, one frame: stereo + 10 GN iterations (PCG to 1e-12) vs oracle (direct)."""
+    gu.say("[e2e] config 0 case 0 f64 line5 N_s=32 rtol 1e-12")
+    kf = gu.make_gpu_kf(c0, "f64", "line5", 32, n_gn=10, cg_rtol=1e-12, cg_max=4000)
+    t = gu.torch()
+    kf.fuse_frame(gu.dev(c0.images[0], t.uint8), c0.poses[0])
+    d, s = kf.read_depth()
+    st = kf.export_state()
+    from oracle import OracleKeyframe
+    ok = OracleKeyframe(c0.K, c0.W, c0.H, StereoParams(n_samples=32, pattern="line5"),
+                        SolverParams(n_gn=10, cg_rtol=1e-12, cg_max=4000, linear_solver="pcg"))
+    ok.set_prior(c0.image0, *c0.priors.maps(), c0.T_wc0)
+    rep = ok.fuse_frame(c0.images[0], c0.poses[0])
+    res = rep.search
+    match = st["match"].cpu().numpy().ravel()[res.pix]
+    mism = np.count_nonzero(match != res.k_best)
+    d_o, s_o = ok.read_depth()
+    err = np.abs(np.log(d.cpu().numpy()) - np.log(d_o))
+    gu.say(f"[e2e-c0] index mismatches {mism} max|dlogd| {err.max():.3e} scale {s:.12f} vs {s_o:.12f}")
+    assert mism == 0
+    assert err.max() <= 1e-10 and abs(np.log(s) - np.log(s_o)) <= 1e-10
+    # and the configured PCG tolerance keeps it within 5e-9 of direct solves
+    x_d, _, _ = fusion.gauss_newton(ok.prior.mu, 0.0, ok.prior, ok.semi(), SolverParams(n_gn=10, linear_solver="direct"))
+    gu.say(f"[e2e-c0] vs direct solves max|dlogd| {np.abs(np.log(d.cpu().numpy()) - x_d).max():.3e}")
+    assert np.abs(np.log(d.cpu().numpy()) - x_d).max() <= 5e-9
