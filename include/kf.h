@@ -82,6 +82,9 @@ typedef struct {
   int32_t n_cg;                 /* PCG iterations per GN iteration when cg_rtol == 0, >= 1 */
   double cg_rtol;               /* > 0: PCG until ||r|| <= cg_rtol ||b||, at most cg_max */
   int32_t cg_max;               /* cap of the tolerance mode, >= 1 */
+  int32_t cg_variant;           /* 0 automatic (pipelined when cg_rtol == 0), 1 textbook PCG,
+                                   2 pipelined PCG: same iterates in exact arithmetic, one team
+                                   synchronisation per iteration instead of two */
   double huber_delta;           /* Huber threshold on whitened residuals (> 0, may be INFINITY) */
   double d_near, d_far;         /* depth range of a full-line search, 0 < d_near < d_far */
   double grad_gate;             /* texture gate: |grad I0| >= grad_gate grey levels per pixel */
@@ -90,6 +93,9 @@ typedef struct {
   int32_t precision;            /* kf_precision */
   int32_t solver_tiles_x;       /* solver workgroup grid (0, 0 = automatic) */
   int32_t solver_tiles_y;
+  int32_t solver_threads;       /* threads per solver workgroup: 0 = automatic, 256 or 1024 */
+  int32_t solver_cooperative;   /* 1: hipLaunchCooperativeKernel; 0: plain launch whose grid is
+                                   checked against the device's co-resident capacity */
   void* stream;                 /* hipStream_t the context enqueues on (NULL = null stream) */
   void* workspace;              /* device buffer of at least kf_workspace_bytes(cfg) bytes */
   size_t workspace_bytes;
@@ -153,6 +159,9 @@ kf_status kf_read_depth(kf_ctx* ctx, void* depth_out, void* var_out, double* sca
 
 /* Statistics of the last stereo update and solve (host struct). Synchronises. */
 kf_status kf_read_stats(kf_ctx* ctx, kf_frame_stats* out);
+
+/* Solver decomposition chosen for ctx: tiles_x, tiles_y, tile_w, tile_h, threads. */
+kf_status kf_solver_layout(const kf_ctx* ctx, int32_t out[5]);
 
 /* Copies the resident state out (device buffers, each nullable): log-depth x,
    inverse depth rho and its variance (0 = no estimate), the last match index per

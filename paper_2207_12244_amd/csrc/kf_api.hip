@@ -21,6 +21,7 @@ struct kf_ctx {
   char* ws;
   uint64_t timeout_ticks;
   int stereo_blocks;
+  int coresident;      // workgroups of the solver tiling the device holds at once (-1: not checked)
 };
 
 namespace kf {
@@ -28,6 +29,10 @@ namespace kf {
 namespace {
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Row stride of the staged new frame: >= W + 8 bytes (room for dword reads past
+// the last pixel), a multiple of 64.
+int stage_stride_impl(int W) { return ((W + 8 + 63) / 64) * 64; }
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
@@ -52,23 +57,28 @@ const char* validate(const kf_config& c) {
   if (c.precision != KF_F64 && c.precision != KF_F32 && c.precision != KF_BF16_F32) return "unknown precision";
   if ((c.solver_tiles_x == 0) != (c.solver_tiles_y == 0) || c.solver_tiles_x < 0 || c.solver_tiles_y < 0)
     return "solver_tiles_x/y must both be 0 (automatic) or both positive";
+  if (c.solver_threads != 0 && c.solver_threads != 256 && c.solver_threads != 1024)
+    return "solver_threads must be 0, 256 or 1024";
+  if (c.solver_cooperative != 0 && c.solver_cooperative != 1) return "solver_cooperative must be 0 or 1";
+  if (c.cg_variant < 0 || c.cg_variant > 2) return "cg_variant must be 0, 1 or 2";
+  if (c.cg_variant == 2 && c.cg_rtol > 0.0) return "the pipelined CG variant runs a fixed iteration count (cg_rtol = 0)";
   return nullptr;
 }
 
-int ppt_for(int px) {
-  const int need = (px + SOLVE_THREADS - 1) / SOLVE_THREADS;
-  static const int opts[] = {1, 2, 3, 4, 5, 6, 8};
+int ppt_for(int px, int threads) {
+  const int need = (px + threads - 1) / threads;
+  static const int opts[] = {1, 2, 3, 4, 6, 8};
   for (int o : opts)
     if (o >= need) return o;
   return 0;
 }
 
-bool tiling_ok(int W, int H, int tx, int ty, Tiling* t) {
-  if (tx < 1 || ty < 1 || tx > W || ty > H || tx * ty > 1024) return false;
+bool tiling_ok(int W, int H, int tx, int ty, int threads, Tiling* t) {
+  if (tx < 1 || ty < 1 || tx > W || ty > H || tx * ty > MAX_TEAM) return false;
   const int tw = (W + tx - 1) / tx, th = (H + ty - 1) / ty;
   if ((tx - 1) * tw >= W || (ty - 1) * th >= H) return false;   // no empty tiles
-  if (tw + th > 1024) return false;                             // ghost ring fits the slots
-  const int ppt = ppt_for(tw * th);
+  if (tw + th > threads) return false;                          // ghost ring fits 2 slots per thread
+  const int ppt = ppt_for(tw * th, threads);
   if (ppt == 0) return false;
   t->tiles_x = tx;
   t->tiles_y = ty;
@@ -76,6 +86,7 @@ bool tiling_ok(int W, int H, int tx, int ty, Tiling* t) {
   t->tile_h = th;
   t->blocks = tx * ty;
   t->ppt = ppt;
+  t->threads = threads;
   return true;
 }
 
@@ -84,31 +95,44 @@ bool tiling_ok(int W, int H, int tx, int ty, Tiling* t) {
 // Picks the tile grid minimising a latency model of one PCG iteration:
 // team synchronisation ~1.1 us + 6.5 ns per workgroup (measured on MI355X)
 // plus the per-workgroup stencil work (~30 VALU ops per pixel at 64 lanes per
-// clock, 2.4 GHz), with a small penalty for long tile perimeters.
-bool choose_tiling(int W, int H, int tx_req, int ty_req, Tiling* t) {
-  if (tx_req > 0 && ty_req > 0) return tiling_ok(W, H, tx_req, ty_req, t);
+// clock, 2.4 GHz; doubled for 256-thread workgroups, whose single wavefront
+// per SIMD hides no latency), with a small penalty for long tile perimeters.
+bool choose_tiling(int W, int H, int tx_req, int ty_req, int threads_req, Tiling* t) {
+  const int thr_opts[2] = {1024, 256};
+  if (tx_req > 0 && ty_req > 0) {
+    for (int nt : thr_opts) {
+      if (threads_req && nt != threads_req) continue;
+      if (tiling_ok(W, H, tx_req, ty_req, nt, t)) return true;
+    }
+    return false;
+  }
   double best = 1e300;
   Tiling bt{};
   bool found = false;
-  for (int tx = 1; tx <= 64 && tx <= W; ++tx) {
-    for (int ty = 1; ty <= 64 && ty <= H; ++ty) {
-      if (tx * ty > 256) break;
-      Tiling c;
-      if (!tiling_ok(W, H, tx, ty, &c)) continue;
-      const double sync_us = 1.1 + 0.0065 * c.blocks;
-      const double work_us = (double)c.tile_w * c.tile_h * 30.0 / 64.0 / 2400.0;
-      const double perim_us = (c.tile_w + c.tile_h) * 1e-4;
-      const double cost = sync_us + work_us + perim_us;
-      if (cost < best) {
-        best = cost;
-        bt = c;
-        found = true;
+  for (int nt : thr_opts) {
+    if (threads_req && nt != threads_req) continue;
+    for (int tx = 1; tx <= 64 && tx <= W; ++tx) {
+      for (int ty = 1; ty <= 64 && ty <= H; ++ty) {
+        if (tx * ty > MAX_TEAM) break;
+        Tiling c;
+        if (!tiling_ok(W, H, tx, ty, nt, &c)) continue;
+        const double sync_us = 1.1 + 0.0065 * c.blocks;
+        const double work_us = (double)c.tile_w * c.tile_h * 30.0 / 64.0 / 2400.0 * (nt == 256 ? 2.0 : 1.0);
+        const double perim_us = (c.tile_w + c.tile_h) * 1e-4;
+        const double cost = sync_us + work_us + perim_us;
+        if (cost < best) {
+          best = cost;
+          bt = c;
+          found = true;
+        }
       }
     }
   }
   if (found) *t = bt;
   return found;
 }
+
+int stage_stride(int W) { return stage_stride_impl(W); }
 
 bool layout_for(const kf_config& c, const Tiling& t, Layout* L) {
   const size_t N = (size_t)c.width * c.height;
@@ -126,6 +150,7 @@ bool layout_for(const kf_config& c, const Tiling& t, Layout* L) {
   L->rho = off; off += align256(N * elt);
   L->var = off; off += align256(N * elt);
   L->match = off; off += align256(N * 4);
+  L->i1s = off; off += align256((size_t)(c.height + 1) * stage_stride(c.width));
   L->scal = off; off += 256;
   L->parts = off; off += align256((size_t)2 * NV_MAX * t.blocks * 2 * 8);
   L->halo = off; off += align256((size_t)2 * t.blocks * (2 * t.tile_w + 2 * t.tile_h) * 2 * 8);
@@ -284,7 +309,7 @@ void kf_config_default(kf_config* cfg, int32_t width, int32_t height) {
 size_t kf_workspace_bytes(const kf_config* cfg) {
   if (!cfg || validate(*cfg)) return 0;
   Tiling t;
-  if (!choose_tiling(cfg->width, cfg->height, cfg->solver_tiles_x, cfg->solver_tiles_y, &t)) return 0;
+  if (!choose_tiling(cfg->width, cfg->height, cfg->solver_tiles_x, cfg->solver_tiles_y, cfg->solver_threads, &t)) return 0;
   Layout L;
   layout_for(*cfg, t, &L);
   return L.total;
@@ -296,7 +321,7 @@ kf_status kf_create(const kf_config* cfg, kf_ctx** out) {
   if (!cfg) return KF_ERR_ARG;
   if (validate(*cfg)) return KF_ERR_ARG;
   Tiling t;
-  if (!choose_tiling(cfg->width, cfg->height, cfg->solver_tiles_x, cfg->solver_tiles_y, &t)) return KF_ERR_ARG;
+  if (!choose_tiling(cfg->width, cfg->height, cfg->solver_tiles_x, cfg->solver_tiles_y, cfg->solver_threads, &t)) return KF_ERR_ARG;
   Layout L;
   layout_for(*cfg, t, &L);
   if (!cfg->workspace) return KF_ERR_ARG;
@@ -318,6 +343,7 @@ kf_status kf_create(const kf_config* cfg, kf_ctx** out) {
     rate_khz = 100000;
   c->timeout_ticks = (uint64_t)rate_khz * 1000ull * 2ull;   // 2 s
   c->stereo_blocks = stereo_grid_blocks(c->device);
+  c->coresident = -1;
   *out = c;
   return KF_OK;
 }
@@ -388,6 +414,8 @@ kf_status kf_stereo_update(kf_ctx* c, const uint8_t* image1, const double T_wc1[
   a.H = c->cfg.height;
   a.i0 = c->ws + c->lay.i0;
   a.i1 = image1;
+  a.i1s = ws_ptr<uint8_t>(c, c->lay.i1s);
+  a.i1_stride = stage_stride(c->cfg.width);
   a.list = ws_ptr<int32_t>(c, c->lay.list);
   a.scal_ro = scal_ptr(c);
   a.scal = scal_ptr(c);
@@ -436,7 +464,12 @@ kf_status kf_solve(kf_ctx* c) {
   a.huber_delta = g.huber_delta;
   a.r_floor = g.r_floor;
   a.timeout_ticks = c->timeout_ticks;
-  hipError_t e = launch_solve(g.precision, c->tiling, a, c->stream);
+  const bool pipelined = g.cg_variant == 2 || (g.cg_variant == 0 && g.cg_rtol == 0.0);
+  if (c->coresident < 0) c->coresident = solve_max_coresident(g.precision, c->tiling, pipelined, c->device);
+  if (c->coresident < c->tiling.blocks)
+    return fail(c, KF_ERR_ARG, "solver tiling needs " + std::to_string(c->tiling.blocks) +
+                               " co-resident workgroups, the device holds " + std::to_string(c->coresident));
+  hipError_t e = launch_solve(g.precision, c->tiling, a, g.solver_cooperative != 0, pipelined, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "kf_solve");
   c->epoch += (uint32_t)bound;
   return KF_OK;
@@ -488,6 +521,16 @@ kf_status kf_read_stats(kf_ctx* c, kf_frame_stats* out) {
   out->cg_rel_residual = h.cg_rel_residual;
   if (h.err & ERR_TIMEOUT) return fail(c, KF_ERR_TIMEOUT, "solver workgroups timed out waiting for their team");
   if (h.err & ERR_INPUT) return fail(c, KF_ERR_INPUT, "device found a non-finite input or a variance <= 0");
+  return KF_OK;
+}
+
+kf_status kf_solver_layout(const kf_ctx* c, int32_t out[5]) {
+  if (!c || !out) return KF_ERR_ARG;
+  out[0] = c->tiling.tiles_x;
+  out[1] = c->tiling.tiles_y;
+  out[2] = c->tiling.tile_w;
+  out[3] = c->tiling.tile_h;
+  out[4] = c->tiling.threads;
   return KF_OK;
 }
 

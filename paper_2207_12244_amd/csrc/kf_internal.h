@@ -46,6 +46,12 @@ template <> __device__ inline double to_img<double, double>(double v) { return v
 template <> __device__ inline float to_img<float, float>(float v) { return v; }
 template <> __device__ inline bf16 to_img<bf16, float>(float v) { return float_to_bf16(v); }
 
+// v rounded to the storage type TI and read back (identity for float/double storage).
+template <typename TI, typename T> __device__ inline T round_to_img(T v) {
+  const TI s = to_img<TI, T>(v);
+  return load_img<TI, T>(&s, 0);
+}
+
 // Form traits: T = map and arithmetic type, TI = keyframe image / patch storage type.
 template <int PREC> struct Form;
 template <> struct Form<KF_F64> { using T = double; using TI = double; };
@@ -70,22 +76,25 @@ enum : int32_t { ERR_INPUT = 1, ERR_TIMEOUT = 2 };
 // ------------------------------------------------------------------ workspace layout
 
 struct Layout {
-  size_t i0, list, chunk, prior, x, rho, var, match, scal, parts, halo, total;
+  size_t i0, list, chunk, prior, x, rho, var, match, i1s, scal, parts, halo, total;
   size_t elt;       // sizeof(T)
   size_t elt_img;   // sizeof(TI)
 };
 
 // Solver decomposition: tiles_x x tiles_y workgroups, each owning one tile.
 struct Tiling {
-  int tiles_x, tiles_y, tile_w, tile_h, blocks, ppt;
+  int tiles_x, tiles_y, tile_w, tile_h, blocks, ppt, threads;
 };
 
-constexpr int SOLVE_THREADS = 256;
 constexpr int NV_MAX = 3;            // values reduced per synchronisation
+constexpr int MAX_TEAM = 256;        // workgroups per keyframe team
 constexpr int CHUNK = 256;           // pixels per compaction chunk
 
-bool choose_tiling(int W, int H, int tx_req, int ty_req, Tiling* t);
+bool choose_tiling(int W, int H, int tx_req, int ty_req, int threads_req, Tiling* t);
+// Workgroups of this tiling the device can hold at once (0 if unknown).
+int solve_max_coresident(int prec, const Tiling& t, bool pipelined, int device);
 bool layout_for(const kf_config& cfg, const Tiling& t, Layout* lay);
+int stage_stride(int W);
 
 // ------------------------------------------------------------------ kernel arguments
 
@@ -114,7 +123,9 @@ struct FrameConst {          // epipolar constants of one frame (host FP64)
 struct StereoArgs {
   int W, H;
   const void* i0;            // TI[N]
-  const uint8_t* i1;         // new frame
+  const uint8_t* i1;         // new frame (caller's buffer)
+  uint8_t* i1s;              // new frame staged with padded rows (H + 1 rows of i1_stride bytes)
+  int i1_stride;
   const int32_t* list;
   const DevScalars* scal_ro;
   DevScalars* scal;
@@ -156,7 +167,8 @@ struct ImportArgs {
 
 hipError_t launch_prior(int prec, const PriorArgs& a, hipStream_t s);
 hipError_t launch_stereo(int prec, int pattern, int ns, const StereoArgs& a, int blocks, hipStream_t s);
-hipError_t launch_solve(int prec, const Tiling& t, const SolveArgs& a, hipStream_t s);
+hipError_t launch_solve(int prec, const Tiling& t, const SolveArgs& a, bool cooperative, bool pipelined,
+                        hipStream_t s);
 hipError_t launch_read(int prec, const ReadArgs& a, hipStream_t s);
 hipError_t launch_import(int prec, const ImportArgs& a, hipStream_t s);
 size_t solve_smem_bytes(int prec, const Tiling& t);

@@ -24,9 +24,7 @@ namespace kf {
 
 namespace {
 
-constexpr int NT = SOLVE_THREADS;
-constexpr int NW = NT / 64;
-constexpr int GMAX = 8;      // ghost slots per thread: ghost ring <= GMAX * NT cells
+constexpr int GMAX = 2;      // ghost slots per thread: ghost ring <= GMAX * threads cells
 
 __device__ inline void st_word(uint64_t* p, uint64_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -54,31 +52,6 @@ template <> struct Wire<double> {
   }
 };
 
-// Spin until the value at w carries epoch e; false on timeout or team abort.
-template <typename V>
-__device__ inline bool wait_get(const uint64_t* w, uint32_t e, V& out, uint64_t limit, const int32_t* err) {
-  uint32_t part[2] = {0u, 0u};
-  const uint64_t t0 = wall_clock64();
-#pragma unroll
-  for (int k = 0; k < Wire<V>::N; ++k) {
-    unsigned spins = 0;
-    uint64_t x;
-    while (true) {
-      x = ld_word(w + k);
-      if ((uint32_t)(x >> 32) == e) break;
-      if ((++spins & 255u) == 0u) {
-        if (wall_clock64() - t0 > limit) return false;
-        if (__hip_atomic_load(const_cast<int32_t*>(err), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
-            ERR_TIMEOUT)
-          return false;
-      }
-    }
-    part[k] = (uint32_t)x;
-  }
-  out = Wire<V>::make(part[0], part[1]);
-  return true;
-}
-
 __device__ inline double wave_sum(double v) {
 #pragma unroll
   for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
@@ -98,18 +71,18 @@ __device__ inline T edge_weight(T xa, T xb, T g, T isd, T delta) {
   return huber_w(r, delta) * isd * isd;
 }
 
-template <typename T>
+template <typename T, int NT>
 struct Team {
+  static constexpr int NW = NT / 64;
+  static constexpr int PSLOTS = (NV_MAX * MAX_TEAM + NT - 1) / NT;   // partial slots polled per thread
   int B, b, tw, th, rw, perim, tile_w, tile_h;
   int nb_up, nb_dn, nb_lf, nb_rt;
   uint64_t* parts;
   uint64_t* halo;
-  const int32_t* err;
-  int32_t* err_w;
+  int32_t* err;
   uint64_t limit;
   double* s_wred;   // [NW][NV_MAX]
   double* s_pol;    // [NV_MAX][B]
-  double* s_tot;    // [NV_MAX]
   int* s_abort;
   // ghost slots of this thread
   int g_src[GMAX];  // neighbour workgroup or -1
@@ -131,9 +104,11 @@ struct Team {
     if (lx == tw - 1 && nb_rt >= 0) Wire<T>::put(halo_slot(e, b, 2 * tile_w + tile_h + ly), val, e);
   }
 
-  // Team-wide sums of nv per-thread partials (fixed summation order) and the
-  // neighbours' published boundary values for this thread's ghost slots.
-  // Returns false if the team has to abort (all threads agree).
+  // Team-wide sums of nv per-thread partials and, if `ghosts`, the neighbours'
+  // published boundary values for this thread's ghost slots. Every wavefront
+  // sums the team's partials itself in the same fixed order, so all threads of
+  // all workgroups hold bit-identical totals. All words a thread waits for are
+  // loaded together each polling round. Returns false if the team aborts.
   __device__ bool sync(uint32_t e, int nv, const double* vals, double* tot, T* gval, bool ghosts) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (int v = 0; v < nv; ++v) {
@@ -141,55 +116,101 @@ struct Team {
       if (lane == 0) s_wred[wave * NV_MAX + v] = s;
     }
     __syncthreads();
-    if (tid == 0) {
-      for (int v = 0; v < nv; ++v) {
-        double p = 0.0;
-        for (int w = 0; w < NW; ++w) p += s_wred[w * NV_MAX + v];
-        Wire<double>::put(part_slot(e, v, b), p, e);
-      }
+    if (tid < nv) {
+      double p = 0.0;
+      for (int w = 0; w < NW; ++w) p += s_wred[w * NV_MAX + tid];
+      Wire<double>::put(part_slot(e, tid, b), p, e);
     }
-    bool ok = true;
-    for (int s = tid; s < nv * B; s += NT) {
-      const int v = s / B, j = s - v * B;
-      double val = 0.0;
-      ok = ok && wait_get<double>(part_slot(e, v, j), e, val, limit, err);
-      s_pol[v * B + j] = val;
-    }
+    // poll set of this thread
+    const int nslots = nv * B;
+    bool p_ready[PSLOTS], g_ready[GMAX];
+    uint64_t pw0[PSLOTS], pw1[PSLOTS], gw0[GMAX], gw1[GMAX];
 #pragma unroll
-    for (int m = 0; m < GMAX; ++m) {
-      if (ghosts && g_src[m] >= 0) {
-        T val = (T)0;
-        ok = ok && wait_get<T>(halo_slot(e, g_src[m], g_off[m]), e, val, limit, err);
-        gval[m] = val;
+    for (int q = 0; q < PSLOTS; ++q) p_ready[q] = tid + q * NT >= nslots;
+#pragma unroll
+    for (int m = 0; m < GMAX; ++m) g_ready[m] = !(ghosts && g_src[m] >= 0);
+    unsigned spins = 0;
+    uint64_t t0 = 0;
+    bool ok = true;
+    while (true) {
+      bool all = true;
+#pragma unroll
+      for (int q = 0; q < PSLOTS; ++q) {
+        if (!p_ready[q]) {
+          const int s = tid + q * NT, v = s / B, j = s - v * B;
+          const uint64_t* w = part_slot(e, v, j);
+          pw0[q] = ld_word(w);
+          pw1[q] = ld_word(w + 1);
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < GMAX; ++m) {
+        if (!g_ready[m]) {
+          const uint64_t* w = halo_slot(e, g_src[m], g_off[m]);
+          gw0[m] = ld_word(w);
+          if (Wire<T>::N == 2) gw1[m] = ld_word(w + 1);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < PSLOTS; ++q) {
+        if (!p_ready[q]) {
+          if ((uint32_t)(pw0[q] >> 32) == e && (uint32_t)(pw1[q] >> 32) == e) {
+            p_ready[q] = true;
+            const int s = tid + q * NT, v = s / B, j = s - v * B;
+            s_pol[v * B + j] = Wire<double>::make((uint32_t)pw0[q], (uint32_t)pw1[q]);
+          } else {
+            all = false;
+          }
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < GMAX; ++m) {
+        if (!g_ready[m]) {
+          if ((uint32_t)(gw0[m] >> 32) == e && (Wire<T>::N == 1 || (uint32_t)(gw1[m] >> 32) == e)) {
+            g_ready[m] = true;
+            gval[m] = Wire<T>::make((uint32_t)gw0[m], (uint32_t)gw1[m]);
+          } else {
+            all = false;
+          }
+        }
+      }
+      if (all) break;
+      if ((++spins & 63u) == 0u) {
+        const uint64_t now = wall_clock64();
+        if (t0 == 0) t0 = now;
+        if (now - t0 > limit ||
+            (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ERR_TIMEOUT)) {
+          ok = false;
+          break;
+        }
       }
     }
     if (!ok) {
       *s_abort = 1;
-      atomicOr(err_w, ERR_TIMEOUT);
+      atomicOr(err, ERR_TIMEOUT);
     }
     __syncthreads();
     if (*s_abort) return false;
-    if (wave < nv) {
+    // every wavefront forms the totals (fixed order, no third barrier)
+    for (int v = 0; v < nv; ++v) {
       double acc = 0.0;
-      for (int j = lane; j < B; j += 64) acc += s_pol[wave * B + j];
-      acc = wave_sum(acc);
-      if (lane == 0) s_tot[wave] = acc;
+      for (int j = lane; j < B; j += 64) acc += s_pol[v * B + j];
+      tot[v] = wave_sum(acc);
     }
-    __syncthreads();
-    for (int v = 0; v < nv; ++v) tot[v] = s_tot[v];
     return true;
   }
 };
 
-template <typename T, int PPT>
+template <typename T, int NT, int PPT, bool PIPE>
 __global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
+  constexpr int NW = NT / 64;
   extern __shared__ __align__(16) unsigned char smem[];
   const int B = a.tiles_x * a.tiles_y;
   const int b = blockIdx.x;
   const int tid = threadIdx.x;
   const int W = a.W, H = a.H, N = W * H;
 
-  Team<T> tm;
+  Team<T, NT> tm;
   tm.B = B;
   tm.b = b;
   const int bx = b % a.tiles_x, by = b / a.tiles_x;
@@ -207,22 +228,22 @@ __global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
   tm.parts = a.parts;
   tm.halo = a.halo;
   tm.err = &a.scal->err;
-  tm.err_w = &a.scal->err;
   tm.limit = a.timeout_ticks;
+  // LDS: [NW][NV_MAX] wave partials, [NV_MAX][B] team partials, abort flag, x and p rings
   double* dsm = reinterpret_cast<double*>(smem);
   tm.s_wred = dsm;
   tm.s_pol = tm.s_wred + NW * NV_MAX;
-  tm.s_tot = tm.s_pol + NV_MAX * B;
-  tm.s_abort = reinterpret_cast<int*>(tm.s_tot + NV_MAX);
+  tm.s_abort = reinterpret_cast<int*>(tm.s_pol + NV_MAX * B);
   const int ring_max = (a.tile_h + 2) * (a.tile_w + 2);
-  T* xs = reinterpret_cast<T*>(dsm + NW * NV_MAX + NV_MAX * B + NV_MAX + 2);
+  T* xs = reinterpret_cast<T*>(dsm + NW * NV_MAX + NV_MAX * B + 2);
   T* ps = xs + ring_max;
+  T* ms0 = ps + ring_max;   // second stencil-operand ring (pipelined variant)
 
   const int tw = tm.tw, th = tm.th, rw = tm.rw;
   const int npx = tw * th;
   const T delta = (T)a.huber_delta;
 
-  for (int i = tid; i < 2 * ring_max; i += NT) xs[i] = (T)0;
+  for (int i = tid; i < 3 * ring_max; i += NT) xs[i] = (T)0;
   if (tid == 0) *tm.s_abort = 0;
 
   // ghost slots: top row, bottom row, left column, right column
@@ -383,7 +404,77 @@ __global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
 
     int it = 0;
     T qv[PPT];
-    while (!converged && it < limit && rz_t != 0.0) {
+    if (PIPE) {
+      // Pipelined Jacobi PCG (Ghysels and Vanroose): the same iterates as the
+      // textbook recurrences in exact arithmetic, with the two inner products
+      // of an iteration reduced together and overlapped with the stencil
+      // product n = A m, so each iteration needs ONE team synchronisation
+      // (partials gamma = r.u, delta = w.u plus the boundary of m).
+      // ps holds u_0 = z_0 (own + ghost ring).
+      T uv[PPT], wv[PPT], mv[PPT], zv[PPT], sv[PPT];
+#pragma unroll
+      for (int j = 0; j < PPT; ++j) {
+        uv[j] = pv[j];
+        wv[j] = mv[j] = zv[j] = sv[j] = qv[j] = (T)0;
+        if (!own[j]) continue;
+        const int l = li[j];
+        const T w = dg[j] * ps[l] - cR[j] * ps[l + 1] - cL[j] * ps[l - 1] - cD[j] * ps[l + rw] - cU[j] * ps[l - rw];
+        wv[j] = w;
+        mv[j] = w * idg[j];
+        ms0[l] = mv[j];
+      }
+      double gamma_prev = 1.0, alpha_prev = 1.0;
+      for (int i = 0; i < limit && !converged; ++i) {
+        T* mring = (i & 1) ? ps : ms0;
+        T* mnext = (i & 1) ? ms0 : ps;
+        double ga = 0.0, de = 0.0;
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+          if (!own[j]) continue;
+          ga += (double)rr[j] * (double)uv[j];
+          de += (double)wv[j] * (double)uv[j];
+          tm.publish(e, lxy[j] & 0xffff, lxy[j] >> 16, mv[j]);
+        }
+        vals[0] = ga; vals[1] = de;
+        if (!tm.sync(e++, 2, vals, tot, gval, true)) return;
+#pragma unroll
+        for (int m = 0; m < GMAX; ++m)
+          if (tm.g_src[m] >= 0) mring[tm.g_li[m]] = gval[m];
+        __syncthreads();
+        if (tot[0] == 0.0) break;
+        double beta = 0.0, alpha;
+        if (i > 0) {
+          beta = tot[0] / gamma_prev;
+          alpha = tot[0] / (tot[1] - beta * tot[0] / alpha_prev);
+        } else {
+          alpha = tot[0] / tot[1];
+        }
+        gamma_prev = tot[0];
+        alpha_prev = alpha;
+        const T al = (T)alpha, be = (T)beta;
+        const bool last = i == limit - 1;
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+          if (!own[j]) continue;
+          pv[j] = i > 0 ? fma(be, pv[j], uv[j]) : uv[j];
+          xr[j] = fma(al, pv[j], xr[j]);
+          if (last) continue;
+          const int l = li[j];
+          const T n = dg[j] * mring[l] - cR[j] * mring[l + 1] - cL[j] * mring[l - 1] - cD[j] * mring[l + rw] -
+                      cU[j] * mring[l - rw];
+          zv[j] = i > 0 ? fma(be, zv[j], n) : n;
+          qv[j] = i > 0 ? fma(be, qv[j], mv[j]) : mv[j];
+          sv[j] = i > 0 ? fma(be, sv[j], wv[j]) : wv[j];
+          rr[j] = fma(-al, sv[j], rr[j]);
+          uv[j] = fma(-al, qv[j], uv[j]);
+          wv[j] = fma(-al, zv[j], wv[j]);
+          mv[j] = wv[j] * idg[j];
+          mnext[l] = mv[j];
+        }
+        ++it;
+      }
+    }
+    while (!PIPE && !converged && it < limit && rz_t != 0.0) {
       // q = A p (5-point stencil; ghost ring holds the neighbours' p)
       double pq = 0.0;
 #pragma unroll
@@ -476,39 +567,59 @@ __global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
   }
 }
 
-template <typename T>
-size_t smem_for(const Tiling& t) {
+size_t smem_for(size_t elt, const Tiling& t) {
   const size_t ring = (size_t)(t.tile_h + 2) * (t.tile_w + 2);
-  return sizeof(double) * (NW * NV_MAX + NV_MAX * (size_t)t.blocks + NV_MAX + 2) + 2 * ring * sizeof(T);
+  return sizeof(double) * ((size_t)(t.threads / 64) * NV_MAX + NV_MAX * (size_t)t.blocks + 2) + 3 * ring * elt;
+}
+
+template <typename T, bool PIPE>
+const void* solve_fn_p(const Tiling& t) {
+#define KF_PPT(nt, n) if (t.threads == nt && t.ppt == n) return reinterpret_cast<const void*>(&k_solve<T, nt, n, PIPE>);
+  KF_PPT(256, 1) KF_PPT(256, 2) KF_PPT(256, 3) KF_PPT(256, 4) KF_PPT(256, 6) KF_PPT(256, 8)
+  KF_PPT(1024, 1) KF_PPT(1024, 2) KF_PPT(1024, 3) KF_PPT(1024, 4) KF_PPT(1024, 6) KF_PPT(1024, 8)
+#undef KF_PPT
+  return nullptr;
 }
 
 template <typename T>
-hipError_t solve_t(const Tiling& t, const SolveArgs& a, hipStream_t s) {
-  const size_t sm = smem_for<T>(t);
+const void* solve_fn(const Tiling& t, bool pipelined) {
+  return pipelined ? solve_fn_p<T, true>(t) : solve_fn_p<T, false>(t);
+}
+
+template <typename T>
+hipError_t solve_t(const Tiling& t, const SolveArgs& a, bool cooperative, bool pipelined, hipStream_t s) {
+  const size_t sm = smem_for(sizeof(T), t);
   void* args[] = {const_cast<SolveArgs*>(&a)};
-  const void* fn = nullptr;
-  switch (t.ppt) {
-#define KF_PPT(n) case n: fn = reinterpret_cast<const void*>(&k_solve<T, n>); break;
-    KF_PPT(1) KF_PPT(2) KF_PPT(3) KF_PPT(4) KF_PPT(5) KF_PPT(6) KF_PPT(8)
-#undef KF_PPT
-    default: return hipErrorInvalidValue;
-  }
+  const void* fn = solve_fn<T>(t, pipelined);
+  if (!fn) return hipErrorInvalidValue;
   if (sm > 48 * 1024) {
     hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
     if (err != hipSuccess) return err;
   }
-  return hipLaunchCooperativeKernel(fn, dim3(t.blocks), dim3(NT), args, (unsigned)sm, s);
+  if (cooperative) return hipLaunchCooperativeKernel(fn, dim3(t.blocks), dim3(t.threads), args, (unsigned)sm, s);
+  return hipLaunchKernel(fn, dim3(t.blocks), dim3(t.threads), args, (unsigned)sm, s);
 }
 
 }  // namespace
 
-size_t solve_smem_bytes(int prec, const Tiling& t) {
-  return prec == KF_F64 ? smem_for<double>(t) : smem_for<float>(t);
+size_t solve_smem_bytes(int prec, const Tiling& t) { return smem_for(prec == KF_F64 ? 8 : 4, t); }
+
+int solve_max_coresident(int prec, const Tiling& t, bool pipelined, int device) {
+  const void* fn = prec == KF_F64 ? solve_fn<double>(t, pipelined) : solve_fn<float>(t, pipelined);
+  if (!fn) return 0;
+  const size_t sm = solve_smem_bytes(prec, t);
+  if (sm > 48 * 1024 && hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm) != hipSuccess)
+    return 0;
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, t.threads, sm) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
+  return per_cu * cus;
 }
 
-hipError_t launch_solve(int prec, const Tiling& t, const SolveArgs& a, hipStream_t s) {
-  if (prec == KF_F64) return solve_t<double>(t, a, s);
-  return solve_t<float>(t, a, s);
+hipError_t launch_solve(int prec, const Tiling& t, const SolveArgs& a, bool cooperative, bool pipelined,
+                        hipStream_t s) {
+  if (prec == KF_F64) return solve_t<double>(t, a, cooperative, pipelined, s);
+  return solve_t<float>(t, a, cooperative, pipelined, s);
 }
 
 }  // namespace kf

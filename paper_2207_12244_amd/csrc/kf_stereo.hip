@@ -26,20 +26,40 @@ struct PixelGeom {
   bool ok;
 };
 
-// Bilinear intensity of the uint8 new frame at (u, v), 0 <= u <= W-1, 0 <= v <= H-1.
+// Bilinear intensity of the staged new frame (uint8, row stride `st`) at
+// (u, v), 0 <= u <= W-1, 0 <= v <= H-1.
 template <typename T>
-__device__ inline T bilin_u8(const uint8_t* img, int W, int H, T u, T v) {
+__device__ inline T bilin_u8(const uint8_t* img, int st, int W, int H, T u, T v) {
   T fu = floor(u), fv = floor(v);
   fu = fu < (T)(W - 2) ? fu : (T)(W - 2);
   fv = fv < (T)(H - 2) ? fv : (T)(H - 2);
   fu = fu > (T)0 ? fu : (T)0;
   fv = fv > (T)0 ? fv : (T)0;
   const T f = u - fu, g = v - fv;
-  const size_t i = (size_t)(int)fv * W + (int)fu;
-  const T i00 = (T)img[i], i10 = (T)img[i + 1], i01 = (T)img[i + W], i11 = (T)img[i + W + 1];
+  const size_t i = (size_t)(int)fv * st + (int)fu;
+  const T i00 = (T)img[i], i10 = (T)img[i + 1], i01 = (T)img[i + st], i11 = (T)img[i + st + 1];
   const T top = i00 + f * (i10 - i00);
   const T bot = i01 + f * (i11 - i01);
   return top + g * (bot - top);
+}
+
+// Six consecutive uint8 taps starting at byte address p of the staged frame
+// (rows are padded, so reading up to 8 bytes past a row's last pixel is in
+// bounds): three aligned dword loads and two byte-aligns.
+template <typename T>
+__device__ inline void taps6(const uint8_t* p, T* t) {
+  const uintptr_t a = reinterpret_cast<uintptr_t>(p);
+  const uint32_t* w = reinterpret_cast<const uint32_t*>(a & ~(uintptr_t)3);
+  const uint32_t sh = (uint32_t)(a & 3u);
+  const uint32_t w0 = w[0], w1 = w[1], w2 = w[2];
+  const uint32_t lo = __builtin_amdgcn_alignbyte(w1, w0, sh);
+  const uint32_t hi = __builtin_amdgcn_alignbyte(w2, w1, sh);
+  t[0] = (T)(lo & 0xffu);
+  t[1] = (T)((lo >> 8) & 0xffu);
+  t[2] = (T)((lo >> 16) & 0xffu);
+  t[3] = (T)(lo >> 24);
+  t[4] = (T)(hi & 0xffu);
+  t[5] = (T)((hi >> 8) & 0xffu);
 }
 
 // Same for the resident keyframe image (storage type TI).
@@ -154,11 +174,37 @@ __device__ inline T point_residual(const StereoArgs& a, const PixelGeom<T>& g, T
     tu = px + (T)(j % 5 - 2);
     tv = py + (T)(j / 5 - 2);
   }
-  return bilin_u8<T>(a.i1, a.W, a.H, tu, tv) - pat_j;
+  return bilin_u8<T>(a.i1s, a.i1_stride, a.W, a.H, tu, tv) - pat_j;
+}
+
+// Keyframe pattern value of point j at pixel (u, v), rounded to the patch storage type.
+// Textured pixels lie >= 2 px inside the image, so every point is in bounds.
+template <typename T, typename TI, int PAT>
+__device__ inline T kf_point(const TI* i0, int W, int H, T u, T v, const PixelGeom<T>& g, int j) {
+  T val;
+  if (PAT == KF_PAT_LINE5) {
+    const T jj = (T)(j - 2);
+    val = bilin_kf<T, TI>(i0, W, H, u + jj * g.l0x, v + jj * g.l0y);
+  } else {
+    const int iu = (int)u + (j % 5 - 2), iv = (int)v + (j / 5 - 2);
+    val = load_img<TI, T>(i0, (size_t)iv * W + iu);
+  }
+  return round_to_img<TI, T>(val);
 }
 
 template <typename T>
 __device__ inline T shfl_xor_t(T v, int m) { return __shfl_xor(v, m, 64); }
+
+// Value of v in lane `src` (wave-uniform) for every lane.
+__device__ inline float readlane_t(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+__device__ inline double readlane_t(double v, int src) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), src);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 template <typename T>
 __device__ inline T shfl_t(T v, int src) { return __shfl(v, src, 64); }
 
@@ -169,8 +215,6 @@ __global__ __launch_bounds__(ST_THREADS) void k_stereo(StereoArgs a) {
   constexpr int GPW = 64 / G;              // pixels per wavefront
   constexpr int P = PAT == KF_PAT_LINE5 ? 5 : 25;
   constexpr T INF = (T)INFINITY;
-
-  __shared__ TI pat_lds[ST_WAVES][GPW][P];
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -185,9 +229,10 @@ __global__ __launch_bounds__(ST_THREADS) void k_stereo(StereoArgs a) {
   T* rho_s = static_cast<T*>(a.rho);
   T* var_s = static_cast<T*>(a.var);
   const int W = a.W, H = a.H;
+  const int st = a.i1_stride;
   int updated_here = 0;
 
-  for (int r = 0; r < rounds; ++r) {      // block-uniform trip count (LDS barriers below)
+  for (int r = 0; r < rounds; ++r) {      // wave-uniform trip count (cross-lane shuffles below)
     const int idx = my_group + r * ngroups;
     const bool active = idx < count;
     const int pix = active ? a.list[idx] : 0;
@@ -197,25 +242,20 @@ __global__ __launch_bounds__(ST_THREADS) void k_stereo(StereoArgs a) {
     PixelGeom<T> g = pixel_geometry<T, PAT, NS>(a, u, v, rho0, var0, has);
     g.ok = g.ok && active;
 
-    // stage the keyframe pattern I0(a_j) in LDS
-    // (textured pixels lie >= 2 px inside the image, so every point is in bounds)
-    for (int j = gl; j < P; j += G) {
-      T val = (T)0;
-      if (active) {
-        if (PAT == KF_PAT_LINE5) {
-          const T jj = (T)(j - 2);
-          val = bilin_kf<T, TI>(i0, W, H, u + jj * g.l0x, v + jj * g.l0y);
-        } else {
-          const int iu = (int)u + (j % 5 - 2), iv = (int)v + (j / 5 - 2);
-          val = load_img<TI, T>(i0, (size_t)iv * W + iu);
-        }
-      }
-      pat_lds[wave][grp][j] = to_img<TI, T>(val);
-    }
-    __syncthreads();
+    // keyframe pattern I0(a_j) (in the form's patch storage type): with at least
+    // P lanes per pixel, lane j evaluates point j and every lane receives all P
+    // values by a cross-lane broadcast (a scalar readlane when one pixel fills
+    // the wavefront); with fewer lanes every lane evaluates all points.
+    T mine = (T)0;
     T pat[P];
+    if (G >= P) {
+      if (gl < P && active) mine = kf_point<T, TI, PAT>(i0, W, H, u, v, g, gl);
 #pragma unroll
-    for (int j = 0; j < P; ++j) pat[j] = load_img<TI, T>(&pat_lds[wave][grp][0], j);
+      for (int j = 0; j < P; ++j) pat[j] = (G == 64) ? readlane_t(mine, j) : shfl_t(mine, grp * G + j);
+    } else {
+#pragma unroll
+      for (int j = 0; j < P; ++j) pat[j] = active ? kf_point<T, TI, PAT>(i0, W, H, u, v, g, j) : (T)0;
+    }
 
     // SSD of this lane's samples
     T ssd[S];
@@ -250,18 +290,12 @@ __global__ __launch_bounds__(ST_THREADS) void k_stereo(StereoArgs a) {
           const T f = px - fpx, gg = py - fpy;
           const int c0 = (int)fpx - 2, r0 = (int)fpy - 2;
           T hprev[5];
+          const uint8_t* base = a.i1s + (size_t)r0 * st + c0;
 #pragma unroll
           for (int n = 0; n < 6; ++n) {
-            int rr = r0 + n;
-            rr = rr < H - 1 ? rr : H - 1;
-            const uint8_t* row = a.i1 + (size_t)rr * W;
+            // rows and the 6th column may reach one pad row / byte (weight 0 there)
             T t[6];
-#pragma unroll
-            for (int m = 0; m < 6; ++m) {
-              int cc = c0 + m;
-              cc = cc < W - 1 ? cc : W - 1;
-              t[m] = (T)row[cc];
-            }
+            taps6<T>(base + (size_t)n * st, t);
             T hrow[5];
 #pragma unroll
             for (int m = 0; m < 5; ++m) hrow[m] = t[m] + f * (t[m + 1] - t[m]);
@@ -328,7 +362,7 @@ __global__ __launch_bounds__(ST_THREADS) void k_stereo(StereoArgs a) {
     T sum_kd = 0, sum_dd = 0;
     if (has_nb) {
       for (int j = gl; j < P; j += G) {
-        const T pj = load_img<TI, T>(&pat_lds[wave][grp][0], j);
+        const T pj = G >= P ? mine : kf_point<T, TI, PAT>(i0, W, H, u, v, g, j);
         const T ek = point_residual<T, PAT>(a, g, pxk, pyk, j, pj);
         const T en = point_residual<T, PAT>(a, g, pxn, pyn, j, pj);
         const T de = en - ek;
@@ -367,11 +401,19 @@ __global__ __launch_bounds__(ST_THREADS) void k_stereo(StereoArgs a) {
         }
       }
     }
-    __syncthreads();   // LDS pattern slot reused next round
   }
   // one atomic per wavefront
   for (int m = 32; m > 0; m >>= 1) updated_here += __shfl_xor(updated_here, m, 64);
   if (lane == 0 && updated_here) atomicAdd(&a.scal->n_updated, updated_here);
+}
+
+// Copies the caller's frame into rows of `st` bytes, zero padded, plus one zero row.
+__global__ void k_stage_frame(const uint8_t* src, uint8_t* dst, int W, int H, int st) {
+  const int total = (H + 1) * st;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+    const int r = i / st, c = i - r * st;
+    dst[i] = (r < H && c < W) ? src[(size_t)r * W + c] : (uint8_t)0;
+  }
 }
 
 template <typename T, typename TI, int PAT>
@@ -402,6 +444,12 @@ int stereo_grid_blocks(int device) {
 }
 
 hipError_t launch_stereo(int prec, int pattern, int ns, const StereoArgs& a, int blocks, hipStream_t s) {
+  {
+    const int total = (a.H + 1) * a.i1_stride;
+    int nb = (total + 255) / 256;
+    nb = nb < 2048 ? nb : 2048;
+    hipLaunchKernelGGL(k_stage_frame, dim3(nb), dim3(256), 0, s, a.i1, a.i1s, a.W, a.H, a.i1_stride);
+  }
   switch (prec) {
     case KF_F64: return stereo_prec<KF_F64>(pattern, ns, a, blocks, s);
     case KF_F32: return stereo_prec<KF_F32>(pattern, ns, a, blocks, s);

@@ -42,12 +42,13 @@ class KfConfig(ctypes.Structure):
         ("fx", c_double), ("fy", c_double), ("cx", c_double), ("cy", c_double),
         ("n_samples", c_int32), ("pattern", c_int32),
         ("n_gn", c_int32), ("n_cg", c_int32),
-        ("cg_rtol", c_double), ("cg_max", c_int32),
+        ("cg_rtol", c_double), ("cg_max", c_int32), ("cg_variant", c_int32),
         ("huber_delta", c_double),
         ("d_near", c_double), ("d_far", c_double),
         ("grad_gate", c_double), ("sigma_photo", c_double), ("r_floor", c_double),
         ("precision", c_int32),
         ("solver_tiles_x", c_int32), ("solver_tiles_y", c_int32),
+        ("solver_threads", c_int32), ("solver_cooperative", c_int32),
         ("stream", c_void_p), ("workspace", c_void_p), ("workspace_bytes", c_size_t),
     ]
 
@@ -93,6 +94,7 @@ def load_library(path: Optional[str] = None):
         "kf_read_depth": (c_int32, [P, P, P, POINTER(c_double)]),
         "kf_read_stats": (c_int32, [P, POINTER(KfFrameStats)]),
         "kf_export_state": (c_int32, [P, P, P, P, P, POINTER(c_double)]),
+        "kf_solver_layout": (c_int32, [P, POINTER(c_int32)]),
         "kf_import_state": (c_int32, [P, P, P, P, POINTER(c_double)]),
     }
     for name, (res, args) in sig.items():
@@ -106,7 +108,7 @@ def load_library(path: Optional[str] = None):
 EXPORTED_SYMBOLS = (
     "kf_config_default", "kf_workspace_bytes", "kf_create", "kf_destroy", "kf_last_error", "kf_status_string",
     "kf_set_prior", "kf_stereo_update", "kf_solve", "kf_fuse_frame", "kf_read_depth", "kf_read_stats",
-    "kf_export_state", "kf_import_state",
+    "kf_export_state", "kf_import_state", "kf_solver_layout",
 )
 
 
@@ -187,6 +189,12 @@ def kf_export_state(ctx, x=None, rho=None, rho_var=None, match=None) -> float:
     return t.value
 
 
+def kf_solver_layout(ctx):
+    out = (c_int32 * 5)()
+    _check(load_library().kf_solver_layout(ctx, out), ctx)
+    return dict(tiles_x=out[0], tiles_y=out[1], tile_w=out[2], tile_h=out[3], threads=out[4])
+
+
 def kf_import_state(ctx, x=None, rho=None, rho_var=None, tau: Optional[float] = None) -> None:
     tp = ctypes.byref(c_double(float(tau))) if tau is not None else None
     _check(load_library().kf_import_state(ctx, x, rho, rho_var, tp), ctx)
@@ -209,7 +217,8 @@ class Keyframe:
     def __init__(self, width: int, height: int, *, precision: str = "f32", pattern: str = "line5",
                  n_samples: int = 32, n_gn: int = 10, n_cg: int = 20, cg_rtol: float = 0.0, cg_max: int = 4000,
                  huber_delta: float = 1.345, d_near: float = 0.4, d_far: float = 10.0, grad_gate: float = 6.0,
-                 sigma_photo: float = 1.0, r_floor: float = 1e-6, K=None, tiles=(0, 0), stream=None):
+                 sigma_photo: float = 1.0, r_floor: float = 1e-6, K=None, tiles=(0, 0), solver_threads: int = 0,
+                 cooperative: bool = False, stream=None):
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("Keyframe needs a GPU (the library has no CPU path)")
@@ -224,6 +233,8 @@ class Keyframe:
         cfg.huber_delta, cfg.d_near, cfg.d_far = float(huber_delta), float(d_near), float(d_far)
         cfg.grad_gate, cfg.sigma_photo, cfg.r_floor = float(grad_gate), float(sigma_photo), float(r_floor)
         cfg.solver_tiles_x, cfg.solver_tiles_y = int(tiles[0]), int(tiles[1])
+        cfg.solver_threads, cfg.solver_cooperative = int(solver_threads), int(bool(cooperative))
+        cfg.cg_variant = {"auto": 0, "textbook": 1, "pipelined": 2}[cg_variant]
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         cfg.stream = c_void_p(self.stream.cuda_stream)
         nbytes = kf_workspace_bytes(cfg)
@@ -286,6 +297,9 @@ class Keyframe:
         v = torch.empty((self.H, self.W), dtype=self.dtype, device="cuda") if with_var else None
         s = kf_read_depth(self.ctx, c_void_p(d.data_ptr()), c_void_p(v.data_ptr()) if v is not None else None)
         return (d, s, v) if with_var else (d, s)
+
+    def solver_layout(self):
+        return kf_solver_layout(self.ctx)
 
     def stats(self) -> KfFrameStats:
         return kf_read_stats(self.ctx)

@@ -32,10 +32,11 @@ def np_map_dtype(precision):
 
 
 def make_gpu_kf(case, precision, pattern, n_samples, n_gn=10, n_cg=20, cg_rtol=0.0, cg_max=4000,
-                tiles=(0, 0), huber_delta=1.345, priors=None):
+                tiles=(0, 0), huber_delta=1.345, priors=None, cg_variant="auto", solver_threads=0):
     from paper_2207_12244_amd.kf import Keyframe
     kf = Keyframe(case.W, case.H, precision=precision, pattern=pattern, n_samples=n_samples, n_gn=n_gn,
-                  n_cg=n_cg, cg_rtol=cg_rtol, cg_max=cg_max, K=case.K, tiles=tiles, huber_delta=huber_delta)
+                  n_cg=n_cg, cg_rtol=cg_rtol, cg_max=cg_max, K=case.K, tiles=tiles, huber_delta=huber_delta,
+                  cg_variant=cg_variant, solver_threads=solver_threads)
     t = torch()
     dt = map_dtype(precision)
     maps = priors if priors is not None else case.priors.maps()

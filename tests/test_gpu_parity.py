@@ -118,8 +118,8 @@ def _oracle_state(case):
     return np.where(ok, r, 0.0), np.where(ok, v, 0.0)
 
 
-@pytest.mark.parametrize("precision,mode", [("f64", "rtol"), ("f64", "fixed"), ("f32", "fixed"),
-                                            ("bf16", "fixed")])
+@pytest.mark.parametrize("precision,mode", [("f64", "rtol"), ("f64", "textbook"), ("f64", "pipelined"),
+                                            ("f32", "textbook"), ("f32", "pipelined"), ("bf16", "pipelined")])
 def test_solver_parity(c0, precision, mode):
     gu.say(f"[solver] config 0 case 0 {precision} {mode}")
     rho, var = _oracle_state(c0)
@@ -129,7 +129,7 @@ def test_solver_parity(c0, precision, mode):
         kf = gu.make_gpu_kf(c0, precision, "line5", 32, n_gn=10, cg_rtol=1e-12, cg_max=4000)
         prm = SolverParams(n_gn=10, cg_rtol=1e-12, cg_max=4000, linear_solver="pcg")
     else:
-        kf = gu.make_gpu_kf(c0, precision, "line5", 32, n_gn=10, n_cg=20)
+        kf = gu.make_gpu_kf(c0, precision, "line5", 32, n_gn=10, n_cg=20, cg_variant=mode)
         prm = SolverParams(n_gn=10, n_cg=20, linear_solver="pcg")
     t = gu.torch()
     mdt = gu.map_dtype(precision)
