@@ -89,6 +89,8 @@ def main(argv=None):
     ap.add_argument("--solver-threads", type=int, default=0, help="solver workgroup size (0 = automatic)")
     ap.add_argument("--cooperative", action="store_true", help="launch the solver cooperatively")
     ap.add_argument("--cg-variant", default="auto", choices=["auto", "textbook", "pipelined"])
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain 256 MiB device-to-device copy (HBM counter calibration)")
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {a.gpus}); "
@@ -104,6 +106,13 @@ def main(argv=None):
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
     wl = WORKLOAD
+    if a.calibrate_copy:
+        # known traffic: reads 256 MiB and writes 256 MiB
+        src = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     t_gen = time.perf_counter()
     case = kfsynth.config_case(wl["config"], 0)
     print(f"# generated {case.W}x{case.H} keyframe + {len(case.images)} frames in "

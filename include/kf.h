@@ -93,7 +93,7 @@ typedef struct {
   int32_t precision;            /* kf_precision */
   int32_t solver_tiles_x;       /* solver workgroup grid (0, 0 = automatic) */
   int32_t solver_tiles_y;
-  int32_t solver_threads;       /* threads per solver workgroup: 0 = automatic, 256 or 1024 */
+  int32_t solver_threads;       /* threads per solver workgroup: 0 = automatic, 256 or 512 */
   int32_t solver_cooperative;   /* 1: hipLaunchCooperativeKernel; 0: plain launch whose grid is
                                    checked against the device's co-resident capacity */
   void* stream;                 /* hipStream_t the context enqueues on (NULL = null stream) */

@@ -57,28 +57,35 @@ const char* validate(const kf_config& c) {
   if (c.precision != KF_F64 && c.precision != KF_F32 && c.precision != KF_BF16_F32) return "unknown precision";
   if ((c.solver_tiles_x == 0) != (c.solver_tiles_y == 0) || c.solver_tiles_x < 0 || c.solver_tiles_y < 0)
     return "solver_tiles_x/y must both be 0 (automatic) or both positive";
-  if (c.solver_threads != 0 && c.solver_threads != 256 && c.solver_threads != 1024)
-    return "solver_threads must be 0, 256 or 1024";
+  if (c.solver_threads != 0 && c.solver_threads != 256 && c.solver_threads != 512)
+    return "solver_threads must be 0, 256 or 512";
   if (c.solver_cooperative != 0 && c.solver_cooperative != 1) return "solver_cooperative must be 0 or 1";
   if (c.cg_variant < 0 || c.cg_variant > 2) return "cg_variant must be 0, 1 or 2";
   if (c.cg_variant == 2 && c.cg_rtol > 0.0) return "the pipelined CG variant runs a fixed iteration count (cg_rtol = 0)";
   return nullptr;
 }
 
-int ppt_for(int px, int threads) {
+// Largest pixels-per-thread whose solver instantiation keeps every value in
+// registers (VGPRs, or AGPRs as spill space for 256-thread workgroups).
+int ppt_max(int prec, int threads) {
+  if (prec == KF_F64) return threads == 256 ? 4 : 2;
+  return threads == 256 ? 6 : 3;
+}
+
+int ppt_for(int px, int threads, int prec) {
   const int need = (px + threads - 1) / threads;
-  static const int opts[] = {1, 2, 3, 4, 6, 8};
+  static const int opts[] = {1, 2, 3, 4, 6};
   for (int o : opts)
-    if (o >= need) return o;
+    if (o >= need) return o <= ppt_max(prec, threads) ? o : 0;
   return 0;
 }
 
-bool tiling_ok(int W, int H, int tx, int ty, int threads, Tiling* t) {
+bool tiling_ok(int W, int H, int tx, int ty, int threads, int prec, Tiling* t) {
   if (tx < 1 || ty < 1 || tx > W || ty > H || tx * ty > MAX_TEAM) return false;
   const int tw = (W + tx - 1) / tx, th = (H + ty - 1) / ty;
   if ((tx - 1) * tw >= W || (ty - 1) * th >= H) return false;   // no empty tiles
   if (tw + th > threads) return false;                          // ghost ring fits 2 slots per thread
-  const int ppt = ppt_for(tw * th, threads);
+  const int ppt = ppt_for(tw * th, threads, prec);
   if (ppt == 0) return false;
   t->tiles_x = tx;
   t->tiles_y = ty;
@@ -95,14 +102,15 @@ bool tiling_ok(int W, int H, int tx, int ty, int threads, Tiling* t) {
 // Picks the tile grid minimising a latency model of one PCG iteration:
 // team synchronisation ~1.1 us + 6.5 ns per workgroup (measured on MI355X)
 // plus the per-workgroup stencil work (~30 VALU ops per pixel at 64 lanes per
-// clock, 2.4 GHz; doubled for 256-thread workgroups, whose single wavefront
-// per SIMD hides no latency), with a small penalty for long tile perimeters.
-bool choose_tiling(int W, int H, int tx_req, int ty_req, int threads_req, Tiling* t) {
-  const int thr_opts[2] = {1024, 256};
+// clock, 2.4 GHz; x2 for 256-thread workgroups, whose single wavefront per
+// SIMD hides no latency, x1.4 for 512 threads), with a small penalty for long
+// tile perimeters.
+bool choose_tiling(int W, int H, int tx_req, int ty_req, int threads_req, int prec, Tiling* t) {
+  const int thr_opts[2] = {512, 256};
   if (tx_req > 0 && ty_req > 0) {
     for (int nt : thr_opts) {
       if (threads_req && nt != threads_req) continue;
-      if (tiling_ok(W, H, tx_req, ty_req, nt, t)) return true;
+      if (tiling_ok(W, H, tx_req, ty_req, nt, prec, t)) return true;
     }
     return false;
   }
@@ -115,9 +123,9 @@ bool choose_tiling(int W, int H, int tx_req, int ty_req, int threads_req, Tiling
       for (int ty = 1; ty <= 64 && ty <= H; ++ty) {
         if (tx * ty > MAX_TEAM) break;
         Tiling c;
-        if (!tiling_ok(W, H, tx, ty, nt, &c)) continue;
+        if (!tiling_ok(W, H, tx, ty, nt, prec, &c)) continue;
         const double sync_us = 1.1 + 0.0065 * c.blocks;
-        const double work_us = (double)c.tile_w * c.tile_h * 30.0 / 64.0 / 2400.0 * (nt == 256 ? 2.0 : 1.0);
+        const double work_us = (double)c.tile_w * c.tile_h * 30.0 / 64.0 / 2400.0 * (nt == 256 ? 2.0 : 1.4);
         const double perim_us = (c.tile_w + c.tile_h) * 1e-4;
         const double cost = sync_us + work_us + perim_us;
         if (cost < best) {
@@ -277,9 +285,6 @@ kf_status check_device_flags(kf_ctx* c) {
 
 }  // namespace
 
-namespace kf {
-hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
-}
 
 extern "C" {
 
@@ -309,7 +314,7 @@ void kf_config_default(kf_config* cfg, int32_t width, int32_t height) {
 size_t kf_workspace_bytes(const kf_config* cfg) {
   if (!cfg || validate(*cfg)) return 0;
   Tiling t;
-  if (!choose_tiling(cfg->width, cfg->height, cfg->solver_tiles_x, cfg->solver_tiles_y, cfg->solver_threads, &t)) return 0;
+  if (!choose_tiling(cfg->width, cfg->height, cfg->solver_tiles_x, cfg->solver_tiles_y, cfg->solver_threads, cfg->precision, &t)) return 0;
   Layout L;
   layout_for(*cfg, t, &L);
   return L.total;
@@ -321,7 +326,7 @@ kf_status kf_create(const kf_config* cfg, kf_ctx** out) {
   if (!cfg) return KF_ERR_ARG;
   if (validate(*cfg)) return KF_ERR_ARG;
   Tiling t;
-  if (!choose_tiling(cfg->width, cfg->height, cfg->solver_tiles_x, cfg->solver_tiles_y, cfg->solver_threads, &t)) return KF_ERR_ARG;
+  if (!choose_tiling(cfg->width, cfg->height, cfg->solver_tiles_x, cfg->solver_tiles_y, cfg->solver_threads, cfg->precision, &t)) return KF_ERR_ARG;
   Layout L;
   layout_for(*cfg, t, &L);
   if (!cfg->workspace) return KF_ERR_ARG;
@@ -436,8 +441,11 @@ kf_status kf_solve(kf_ctx* c) {
   const kf_config& g = c->cfg;
   const uint64_t limit = g.cg_rtol > 0.0 ? (uint64_t)g.cg_max : (uint64_t)g.n_cg;
   const uint64_t bound = (uint64_t)g.n_gn * (2 * limit + 2) + 2;
+  // c->epoch mirrors the device-side base (both advance by `bound` per launch);
+  // before the 32-bit epochs could wrap, clear the exchange words and restart at 1
   if ((uint64_t)c->epoch + bound >= 0xfff00000ull) {
     hipError_t e = launch_zero(c->ws + c->lay.parts, c->lay.total - c->lay.parts, c->stream);
+    if (e == hipSuccess) e = launch_set_u32(&scal_ptr(c)->epoch, 1u, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "kf_solve (epoch wrap)");
     c->epoch = 1;
   }
@@ -456,7 +464,8 @@ kf_status kf_solve(kf_ctx* c) {
   a.parts = ws_ptr<uint64_t>(c, c->lay.parts);
   a.halo = ws_ptr<uint64_t>(c, c->lay.halo);
   a.perim = 2 * c->tiling.tile_w + 2 * c->tiling.tile_h;
-  a.epoch0 = c->epoch;
+  a.epoch_span = (uint32_t)bound;
+  a.packed = (g.precision != KF_F64 && bound < 30000) ? 1 : 0;
   a.n_gn = g.n_gn;
   a.n_cg = g.n_cg;
   a.cg_max = g.cg_max;

@@ -69,7 +69,8 @@ struct DevScalars {
   int32_t n_valid;        // pixels with a filter estimate (computed by the solver)
   int32_t cg_iterations;
   int32_t err;            // bit flags, ERR_*
-  int32_t pad[7];
+  uint32_t epoch;         // next synchronisation epoch of the solver team (never 0)
+  int32_t pad[6];
 };
 enum : int32_t { ERR_INPUT = 1, ERR_TIMEOUT = 2 };
 
@@ -90,7 +91,7 @@ constexpr int NV_MAX = 3;            // values reduced per synchronisation
 constexpr int MAX_TEAM = 256;        // workgroups per keyframe team
 constexpr int CHUNK = 256;           // pixels per compaction chunk
 
-bool choose_tiling(int W, int H, int tx_req, int ty_req, int threads_req, Tiling* t);
+bool choose_tiling(int W, int H, int tx_req, int ty_req, int threads_req, int prec, Tiling* t);
 // Workgroups of this tiling the device can hold at once (0 if unknown).
 int solve_max_coresident(int prec, const Tiling& t, bool pipelined, int device);
 bool layout_for(const kf_config& cfg, const Tiling& t, Layout* lay);
@@ -143,7 +144,8 @@ struct SolveArgs {
   uint64_t* parts;           // [2][NV_MAX][blocks][2] exchange words
   uint64_t* halo;            // [2][blocks][perim][2]
   int perim;                 // 2 tile_w + 2 tile_h
-  uint32_t epoch0;
+  uint32_t epoch_span;       // epochs one launch may use (the base lives in DevScalars::epoch)
+  int packed;                // 1: one-word partials (48-bit values, 16-bit epochs)
   int n_gn, n_cg, cg_max;
   double cg_rtol;
   double huber_delta, r_floor;
@@ -171,6 +173,8 @@ hipError_t launch_solve(int prec, const Tiling& t, const SolveArgs& a, bool coop
                         hipStream_t s);
 hipError_t launch_read(int prec, const ReadArgs& a, hipStream_t s);
 hipError_t launch_import(int prec, const ImportArgs& a, hipStream_t s);
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+hipError_t launch_set_u32(uint32_t* p, uint32_t v, hipStream_t s);
 size_t solve_smem_bytes(int prec, const Tiling& t);
 int stereo_grid_blocks(int device);
 

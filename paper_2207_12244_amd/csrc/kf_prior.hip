@@ -56,6 +56,7 @@ __global__ __launch_bounds__(CHUNK) void k_prior_init(PriorArgs a) {
   const int cnt = __syncthreads_count(m ? 1 : 0);
   if (threadIdx.x == 0) a.chunk_counts[blockIdx.x] = cnt;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.scal->epoch = 1u;
     a.scal->tau = 0.0;
     a.scal->cg_rel_residual = 0.0;
     a.scal->n_updated = 0;
@@ -190,6 +191,13 @@ __global__ void k_zero_words(uint32_t* p, size_t n) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0u;
 }
 }  // namespace
+
+__global__ void k_set_u32(uint32_t* p, uint32_t v) { *p = v; }
+
+hipError_t launch_set_u32(uint32_t* p, uint32_t v, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, p, v);
+  return hipGetLastError();
+}
 
 // Clears a 4-byte aligned device range with a kernel (no memset node, so a
 // stream that is being captured into a graph replays it correctly).

@@ -40,6 +40,21 @@ template <> struct Wire<float> {
   __device__ static void put(uint64_t* w, float v, uint32_t e) { st_word(w, tagged(__float_as_uint(v), e)); }
   __device__ static float make(uint32_t lo, uint32_t) { return __uint_as_float(lo); }
 };
+// One-word transport of an FP64 partial: the top 48 bits of the double
+// (rounded; relative precision 2^-37) and a 16-bit epoch. Used when a launch
+// spans fewer than 30000 epochs, so a slot's previous content is never 2^16
+// epochs old.
+struct Packed48 {
+  __device__ static uint64_t make_word(double v, uint32_t e) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v) + 0x8000ull;
+    return ((uint64_t)(e & 0xffffu) << 48) | (b >> 16);
+  }
+  __device__ static bool ready(uint64_t w, uint32_t e) { return (uint32_t)(w >> 48) == (e & 0xffffu); }
+  __device__ static double value(uint64_t w) {
+    return __longlong_as_double((long long)((w & 0xffffffffffffull) << 16));
+  }
+};
+
 template <> struct Wire<double> {
   static constexpr int N = 2;
   __device__ static void put(uint64_t* w, double v, uint32_t e) {
@@ -52,10 +67,30 @@ template <> struct Wire<double> {
   }
 };
 
+// Data-parallel-primitive move of both halves of a double (out-of-row lanes read 0).
+template <int CTRL, int ROW_MASK, bool BOUND_ZERO>
+__device__ inline double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, ROW_MASK, 0xf, BOUND_ZERO);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xf, BOUND_ZERO);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the 64 lanes, returned in every lane, in a fixed order: an
+// inclusive scan inside each 16-lane row (shifts 1, 2, 4, 8), then the row
+// totals are carried with the row broadcasts 15 and 31; lane 63 ends with the
+// total, which is read back as a scalar.
 __device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
-  return v;
+  v += dpp_d<0x111, 0xf, true>(v);   // row_shr:1
+  v += dpp_d<0x112, 0xf, true>(v);   // row_shr:2
+  v += dpp_d<0x114, 0xf, true>(v);   // row_shr:4
+  v += dpp_d<0x118, 0xf, true>(v);   // row_shr:8
+  v += dpp_d<0x142, 0xa, false>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_d<0x143, 0xc, false>(v);  // row_bcast:31 into rows 2 and 3
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
 template <typename T>
@@ -81,6 +116,7 @@ struct Team {
   uint64_t* halo;
   int32_t* err;
   uint64_t limit;
+  bool packed;      // one-word partials (Packed48) instead of two words
   double* s_wred;   // [NW][NV_MAX]
   double* s_pol;    // [NV_MAX][B]
   int* s_abort;
@@ -109,7 +145,7 @@ struct Team {
   // sums the team's partials itself in the same fixed order, so all threads of
   // all workgroups hold bit-identical totals. All words a thread waits for are
   // loaded together each polling round. Returns false if the team aborts.
-  __device__ bool sync(uint32_t e, int nv, const double* vals, double* tot, T* gval, bool ghosts) {
+  __device__ bool sync(uint32_t e, int nv, const double* vals, double* tot, T* gval, bool ghosts, T* ring = nullptr) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (int v = 0; v < nv; ++v) {
       const double s = wave_sum(vals[v]);
@@ -119,7 +155,8 @@ struct Team {
     if (tid < nv) {
       double p = 0.0;
       for (int w = 0; w < NW; ++w) p += s_wred[w * NV_MAX + tid];
-      Wire<double>::put(part_slot(e, tid, b), p, e);
+      if (packed) st_word(part_slot(e, tid, b), Packed48::make_word(p, e));
+      else Wire<double>::put(part_slot(e, tid, b), p, e);
     }
     // poll set of this thread
     const int nslots = nv * B;
@@ -140,7 +177,7 @@ struct Team {
           const int s = tid + q * NT, v = s / B, j = s - v * B;
           const uint64_t* w = part_slot(e, v, j);
           pw0[q] = ld_word(w);
-          pw1[q] = ld_word(w + 1);
+          if (!packed) pw1[q] = ld_word(w + 1);
         }
       }
 #pragma unroll
@@ -154,10 +191,12 @@ struct Team {
 #pragma unroll
       for (int q = 0; q < PSLOTS; ++q) {
         if (!p_ready[q]) {
-          if ((uint32_t)(pw0[q] >> 32) == e && (uint32_t)(pw1[q] >> 32) == e) {
+          if (packed ? Packed48::ready(pw0[q], e)
+                     : ((uint32_t)(pw0[q] >> 32) == e && (uint32_t)(pw1[q] >> 32) == e)) {
             p_ready[q] = true;
             const int s = tid + q * NT, v = s / B, j = s - v * B;
-            s_pol[v * B + j] = Wire<double>::make((uint32_t)pw0[q], (uint32_t)pw1[q]);
+            s_pol[v * B + j] = packed ? Packed48::value(pw0[q])
+                                      : Wire<double>::make((uint32_t)pw0[q], (uint32_t)pw1[q]);
           } else {
             all = false;
           }
@@ -169,6 +208,7 @@ struct Team {
           if ((uint32_t)(gw0[m] >> 32) == e && (Wire<T>::N == 1 || (uint32_t)(gw1[m] >> 32) == e)) {
             g_ready[m] = true;
             gval[m] = Wire<T>::make((uint32_t)gw0[m], (uint32_t)gw1[m]);
+            if (ring) ring[g_li[m]] = gval[m];
           } else {
             all = false;
           }
@@ -229,7 +269,9 @@ __global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
   tm.halo = a.halo;
   tm.err = &a.scal->err;
   tm.limit = a.timeout_ticks;
-  // LDS: [NW][NV_MAX] wave partials, [NV_MAX][B] team partials, abort flag, x and p rings
+  tm.packed = a.packed != 0;
+  // LDS: [NW][NV_MAX] wave partials, [NV_MAX][B] team partials, abort flag,
+  // then three rings of (tile_h + 2) x (tile_w + 2): x, and two stencil operands
   double* dsm = reinterpret_cast<double*>(smem);
   tm.s_wred = dsm;
   tm.s_pol = tm.s_wred + NW * NV_MAX;
@@ -237,7 +279,7 @@ __global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
   const int ring_max = (a.tile_h + 2) * (a.tile_w + 2);
   T* xs = reinterpret_cast<T*>(dsm + NW * NV_MAX + NV_MAX * B + 2);
   T* ps = xs + ring_max;
-  T* ms0 = ps + ring_max;   // second stencil-operand ring (pipelined variant)
+  T* ms0 = ps + ring_max;
 
   const int tw = tm.tw, th = tm.th, rw = tm.rw;
   const int npx = tw * th;
@@ -282,32 +324,22 @@ __global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
   const T* rho_g = static_cast<const T*>(a.rho);
   const T* var_g = static_cast<const T*>(a.var);
 
-  // per-pixel registers
-  int gi[PPT], li[PPT], lxy[PPT];
-  bool own[PPT];
-  T xr[PPT], rr[PPT], pv[PPT], dg[PPT], idg[PPT], cR[PPT], cL[PPT], cD[PPT], cU[PPT], zs[PPT], isr[PPT];
+  // per-pixel registers; pixel j of this thread is k = tid + j NT of the tile
+  int lxy[PPT];   // (ly << 16) | lx, or -1 when the thread has no j-th pixel
+  T xr[PPT], rr[PPT], pv[PPT], dg[PPT], idg[PPT], cR[PPT], cL[PPT], cD[PPT], cU[PPT];
   const T r_floor = (T)a.r_floor;
+#define KF_LX(j) (lxy[j] & 0xffff)
+#define KF_LY(j) (lxy[j] >> 16)
+#define KF_LI(j) ((KF_LY(j) + 1) * rw + KF_LX(j) + 1)
+#define KF_GI(j) ((oy + KF_LY(j)) * W + ox + KF_LX(j))
 #pragma unroll
   for (int j = 0; j < PPT; ++j) {
     const int k = tid + j * NT;
-    own[j] = k < npx;
-    const int lx = own[j] ? k % tw : 0, ly = own[j] ? k / tw : 0;
-    lxy[j] = (ly << 16) | lx;
-    gi[j] = (oy + ly) * W + ox + lx;
-    li[j] = (ly + 1) * rw + lx + 1;
-    xr[j] = rr[j] = pv[j] = dg[j] = idg[j] = cR[j] = cL[j] = cD[j] = cU[j] = zs[j] = isr[j] = (T)0;
-    if (own[j]) {
-      xr[j] = x_g[gi[j]];
-      xs[li[j]] = xr[j];
-      // semi-dense measurement in log space (Sec. II-B last step): z = -ln rho, R = v / rho^2
-      const T v = var_g[gi[j]];
-      if (v > (T)0) {
-        const T rho = rho_g[gi[j]];
-        zs[j] = -log(rho);
-        T R = v / (rho * rho);
-        R = R > r_floor ? R : r_floor;
-        isr[j] = (T)1 / sqrt(R);
-      }
+    lxy[j] = k < npx ? (((k / tw) << 16) | (k % tw)) : -1;
+    xr[j] = rr[j] = pv[j] = dg[j] = idg[j] = cR[j] = cL[j] = cD[j] = cU[j] = (T)0;
+    if (lxy[j] >= 0) {
+      xr[j] = x_g[KF_GI(j)];
+      xs[KF_LI(j)] = xr[j];
     }
   }
   // ghost x straight from the state (consistent at launch)
@@ -322,7 +354,10 @@ __global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
   double tau = a.scal->tau;
   __syncthreads();
 
-  uint32_t e = a.epoch0;
+  // epoch base of this launch: written by the previous launch's workgroup 0
+  // after its team finished, so every workgroup here reads the same value
+  const uint32_t e0 = a.scal->epoch;
+  uint32_t e = e0;
   const bool tol_mode = a.cg_rtol > 0.0;
   const int limit = tol_mode ? a.cg_max : a.n_cg;
   int cg_total = 0;
@@ -331,68 +366,76 @@ __global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
   double vals[NV_MAX], tot[NV_MAX];
   T gval[GMAX];
 
+  // semi-dense measurement in log space (Sec. II-B last step): z = -ln rho,
+  // R = max(v / rho^2, R_floor); returns 1/sqrt(R), 0 when the pixel has none
+  auto semi = [&](int gi, T& z) -> T {
+    const T v = var_g[gi];
+    if (!(v > (T)0)) {
+      z = (T)0;
+      return (T)0;
+    }
+    const T rho = rho_g[gi];
+    z = -log(rho);
+    T R = v / (rho * rho);
+    R = R > r_floor ? R : r_floor;
+    return (T)1 / sqrt(R);
+  };
+
   for (int gn = 0; gn < a.n_gn; ++gn) {
-    // ---- IRLS weights and 5-point normal equations at (x, tau) (Sec. II-C)
+    // ---- IRLS weights and 5-point normal equations at (x, tau) (Sec. II-C);
+    //      r = b - A x, z = r / diag, p = z
     double rz = 0.0, r2 = 0.0, b2 = 0.0;
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
-      if (!own[j]) continue;
-      const int lx = lxy[j] & 0xffff, ly = lxy[j] >> 16;
-      const int u = ox + lx, v = oy + ly;
-      const int i = gi[j];
+      if (lxy[j] < 0) continue;
+      const int u = ox + KF_LX(j), v = oy + KF_LY(j);
+      const int i = KF_GI(j), l = KF_LI(j);
       const T xi = xr[j];
       const T mu = mu_g[i], isn = isn_g[i];
       const T wn = huber_w((xi - mu) * isn, delta) * isn * isn;
+      T zs;
+      const T isr = semi(i, zs);
       T ws = (T)0;
-      if (isr[j] > (T)0) ws = huber_w((xi - (T)tau - zs[j]) * isr[j], delta) * isr[j] * isr[j];
-      T bb = wn * mu + ws * ((T)tau + zs[j]);
+      if (isr > (T)0) ws = huber_w((xi - (T)tau - zs) * isr, delta) * isr * isr;
+      T bb = wn * mu + ws * ((T)tau + zs);
       T cr = 0, cl = 0, cd = 0, cu = 0;
       if (u < W - 1) {
         const T g = gx_g[i];
-        cr = edge_weight(xi, xs[li[j] + 1], g, isgx_g[i], delta);
+        cr = edge_weight(xi, xs[l + 1], g, isgx_g[i], delta);
         bb -= cr * g;
       }
       if (u > 0) {
         const T g = gx_g[i - 1];
-        cl = edge_weight(xs[li[j] - 1], xi, g, isgx_g[i - 1], delta);
+        cl = edge_weight(xs[l - 1], xi, g, isgx_g[i - 1], delta);
         bb += cl * g;
       }
       if (v < H - 1) {
         const T g = gy_g[i];
-        cd = edge_weight(xi, xs[li[j] + rw], g, isgy_g[i], delta);
+        cd = edge_weight(xi, xs[l + rw], g, isgy_g[i], delta);
         bb -= cd * g;
       }
       if (v > 0) {
         const T g = gy_g[i - W];
-        cu = edge_weight(xs[li[j] - rw], xi, g, isgy_g[i - W], delta);
+        cu = edge_weight(xs[l - rw], xi, g, isgy_g[i - W], delta);
         bb += cu * g;
       }
       const T d = wn + ws + cr + cl + cd + cu;
       dg[j] = d;
       idg[j] = (T)1 / d;
       cR[j] = cr; cL[j] = cl; cD[j] = cd; cU[j] = cu;
-      // r = b - A x, z = r / diag, p = z
-      const T ax = d * xi - cr * xs[li[j] + 1] - cl * xs[li[j] - 1] - cd * xs[li[j] + rw] - cu * xs[li[j] - rw];
+      const T ax = d * xi - cr * xs[l + 1] - cl * xs[l - 1] - cd * xs[l + rw] - cu * xs[l - rw];
       const T r = bb - ax;
       rr[j] = r;
       const T z = r * idg[j];
       pv[j] = z;
+      ps[l] = z;
+      tm.publish(e, KF_LX(j), KF_LY(j), z);
       rz += (double)r * (double)z;
       r2 += (double)r * (double)r;
       b2 += (double)bb * (double)bb;
     }
-    __syncthreads();   // all reads of xs done before ps is written (distinct arrays; kept for clarity)
-#pragma unroll
-    for (int j = 0; j < PPT; ++j) {
-      if (!own[j]) continue;
-      ps[li[j]] = pv[j];
-      tm.publish(e, lxy[j] & 0xffff, lxy[j] >> 16, pv[j]);
-    }
     vals[0] = rz; vals[1] = r2; vals[2] = b2;
-    if (!tm.sync(e++, tol_mode ? 3 : 1, vals, tot, gval, true)) return;
-#pragma unroll
-    for (int m = 0; m < GMAX; ++m)
-      if (tm.g_src[m] >= 0) ps[tm.g_li[m]] = gval[m];
+    if (!tm.sync(e++, tol_mode ? 3 : 1, vals, tot, gval, true, ps)) return;
     double rz_t = tot[0];
     const double bnorm = tol_mode ? sqrt(tot[2]) : 0.0;
     bool converged = false;
@@ -400,7 +443,6 @@ __global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
       relres = bnorm > 0.0 ? sqrt(tot[1]) / bnorm : 0.0;
       converged = sqrt(tot[1]) <= a.cg_rtol * bnorm;
     }
-    __syncthreads();
 
     int it = 0;
     T qv[PPT];
@@ -416,9 +458,9 @@ __global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
       for (int j = 0; j < PPT; ++j) {
         uv[j] = pv[j];
         wv[j] = mv[j] = zv[j] = sv[j] = qv[j] = (T)0;
-        if (!own[j]) continue;
-        const int l = li[j];
-        const T w = dg[j] * ps[l] - cR[j] * ps[l + 1] - cL[j] * ps[l - 1] - cD[j] * ps[l + rw] - cU[j] * ps[l - rw];
+        if (lxy[j] < 0) continue;
+        const int l = KF_LI(j);
+        const T w = dg[j] * uv[j] - cR[j] * ps[l + 1] - cL[j] * ps[l - 1] - cD[j] * ps[l + rw] - cU[j] * ps[l - rw];
         wv[j] = w;
         mv[j] = w * idg[j];
         ms0[l] = mv[j];
@@ -430,17 +472,14 @@ __global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
         double ga = 0.0, de = 0.0;
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
-          if (!own[j]) continue;
+          if (lxy[j] < 0) continue;
           ga += (double)rr[j] * (double)uv[j];
           de += (double)wv[j] * (double)uv[j];
-          tm.publish(e, lxy[j] & 0xffff, lxy[j] >> 16, mv[j]);
+          tm.publish(e, KF_LX(j), KF_LY(j), mv[j]);
         }
         vals[0] = ga; vals[1] = de;
-        if (!tm.sync(e++, 2, vals, tot, gval, true)) return;
-#pragma unroll
-        for (int m = 0; m < GMAX; ++m)
-          if (tm.g_src[m] >= 0) mring[tm.g_li[m]] = gval[m];
-        __syncthreads();
+        // the neighbours' m lands directly in the ghost ring of mring
+        if (!tm.sync(e++, 2, vals, tot, gval, true, mring)) return;
         if (tot[0] == 0.0) break;
         double beta = 0.0, alpha;
         if (i > 0) {
@@ -455,12 +494,12 @@ __global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
         const bool last = i == limit - 1;
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
-          if (!own[j]) continue;
+          if (lxy[j] < 0) continue;
           pv[j] = i > 0 ? fma(be, pv[j], uv[j]) : uv[j];
           xr[j] = fma(al, pv[j], xr[j]);
           if (last) continue;
-          const int l = li[j];
-          const T n = dg[j] * mring[l] - cR[j] * mring[l + 1] - cL[j] * mring[l - 1] - cD[j] * mring[l + rw] -
+          const int l = KF_LI(j);
+          const T n = dg[j] * mv[j] - cR[j] * mring[l + 1] - cL[j] * mring[l - 1] - cD[j] * mring[l + rw] -
                       cU[j] * mring[l - rw];
           zv[j] = i > 0 ? fma(be, zv[j], n) : n;
           qv[j] = i > 0 ? fma(be, qv[j], mv[j]) : mv[j];
@@ -480,8 +519,8 @@ __global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
 #pragma unroll
       for (int j = 0; j < PPT; ++j) {
         qv[j] = (T)0;
-        if (!own[j]) continue;
-        const int l = li[j];
+        if (lxy[j] < 0) continue;
+        const int l = KF_LI(j);
         const T q = dg[j] * pv[j] - cR[j] * ps[l + 1] - cL[j] * ps[l - 1] - cD[j] * ps[l + rw] - cU[j] * ps[l - rw];
         qv[j] = q;
         pq += (double)pv[j] * (double)q;
@@ -493,7 +532,7 @@ __global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
       double rzn = 0.0, rrn = 0.0;
 #pragma unroll
       for (int j = 0; j < PPT; ++j) {
-        if (!own[j]) continue;
+        if (lxy[j] < 0) continue;
         xr[j] += al * pv[j];
         rr[j] -= al * qv[j];
         const T z = rr[j] * idg[j];
@@ -505,8 +544,9 @@ __global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
       if (!tol_mode && it == limit) break;
 #pragma unroll
       for (int j = 0; j < PPT; ++j)
-        if (own[j]) tm.publish(e, lxy[j] & 0xffff, lxy[j] >> 16, qv[j]);
+        if (lxy[j] >= 0) tm.publish(e, KF_LX(j), KF_LY(j), qv[j]);
       vals[0] = rzn; vals[1] = rrn;
+      // ghost z arrives in gval: the ghost copy of p needs beta first
       if (!tm.sync(e++, tol_mode ? 2 : 1, vals, tot, gval, true)) return;
       if (tol_mode) {
         relres = bnorm > 0.0 ? sqrt(tot[1]) / bnorm : 0.0;
@@ -519,9 +559,9 @@ __global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
       rz_t = tot[0];
 #pragma unroll
       for (int j = 0; j < PPT; ++j) {
-        if (!own[j]) continue;
+        if (lxy[j] < 0) continue;
         pv[j] = fma(be, pv[j], qv[j]);
-        ps[li[j]] = pv[j];
+        ps[KF_LI(j)] = pv[j];
       }
 #pragma unroll
       for (int m = 0; m < GMAX; ++m)
@@ -534,38 +574,46 @@ __global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
     double num = 0.0, den = 0.0, cnt = 0.0;
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
-      if (!own[j]) continue;
-      if (isr[j] > (T)0) {
-        const T w = huber_w((xr[j] - (T)tau - zs[j]) * isr[j], delta) * isr[j] * isr[j];
-        num += (double)w * (double)(xr[j] - zs[j]);
+      if (lxy[j] < 0) continue;
+      T zs;
+      const T isr = semi(KF_GI(j), zs);
+      if (isr > (T)0) {
+        const T w = huber_w((xr[j] - (T)tau - zs) * isr, delta) * isr * isr;
+        num += (double)w * (double)(xr[j] - zs);
         den += (double)w;
         cnt += 1.0;
       }
-      tm.publish(e, lxy[j] & 0xffff, lxy[j] >> 16, xr[j]);
+      xs[KF_LI(j)] = xr[j];
+      tm.publish(e, KF_LX(j), KF_LY(j), xr[j]);
     }
     vals[0] = num; vals[1] = den; vals[2] = cnt;
-    if (!tm.sync(e++, 3, vals, tot, gval, true)) return;
+    // the neighbours' x lands directly in the ghost ring of xs
+    if (!tm.sync(e++, 3, vals, tot, gval, true, xs)) return;
     if (tot[1] > 0.0) tau = tot[0] / tot[1];
     n_valid = tot[2];
-#pragma unroll
-    for (int j = 0; j < PPT; ++j)
-      if (own[j]) xs[li[j]] = xr[j];
-#pragma unroll
-    for (int m = 0; m < GMAX; ++m)
-      if (tm.g_src[m] >= 0) xs[tm.g_li[m]] = gval[m];
-    __syncthreads();
   }
 
 #pragma unroll
   for (int j = 0; j < PPT; ++j)
-    if (own[j]) x_g[gi[j]] = xr[j];
+    if (lxy[j] >= 0) x_g[KF_GI(j)] = xr[j];
+#undef KF_LX
+#undef KF_LY
+#undef KF_LI
+#undef KF_GI
   if (b == 0 && tid == 0) {
+    // every member has read e0 before its first publish, and workgroup 0
+    // passed the last synchronisation, so no member still needs the old base
+    a.scal->epoch = e0 + a.epoch_span;
     a.scal->tau = tau;
     a.scal->cg_iterations = cg_total;
     a.scal->cg_rel_residual = relres;
     a.scal->n_valid = (int32_t)n_valid;
   }
 }
+
+}  // namespace
+
+namespace {
 
 size_t smem_for(size_t elt, const Tiling& t) {
   const size_t ring = (size_t)(t.tile_h + 2) * (t.tile_w + 2);
@@ -575,8 +623,12 @@ size_t smem_for(size_t elt, const Tiling& t) {
 template <typename T, bool PIPE>
 const void* solve_fn_p(const Tiling& t) {
 #define KF_PPT(nt, n) if (t.threads == nt && t.ppt == n) return reinterpret_cast<const void*>(&k_solve<T, nt, n, PIPE>);
-  KF_PPT(256, 1) KF_PPT(256, 2) KF_PPT(256, 3) KF_PPT(256, 4) KF_PPT(256, 6) KF_PPT(256, 8)
-  KF_PPT(1024, 1) KF_PPT(1024, 2) KF_PPT(1024, 3) KF_PPT(1024, 4) KF_PPT(1024, 6) KF_PPT(1024, 8)
+  // combinations whose registers fit without scratch spills (see ppt_max)
+  KF_PPT(256, 1) KF_PPT(256, 2) KF_PPT(256, 3) KF_PPT(256, 4)
+  KF_PPT(512, 1) KF_PPT(512, 2)
+  if (sizeof(T) == 4) {
+    KF_PPT(256, 6) KF_PPT(512, 3)
+  }
 #undef KF_PPT
   return nullptr;
 }

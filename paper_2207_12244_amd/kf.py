@@ -16,7 +16,7 @@ from typing import Optional
 
 import numpy as np
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libkf.so")
+LIB_PATH = os.environ.get("KF_LIBRARY") or os.path.join(os.path.dirname(os.path.abspath(__file__)), "libkf.so")
 
 KF_OK = 0
 KF_ERR_ARG = -1
@@ -218,7 +218,7 @@ class Keyframe:
                  n_samples: int = 32, n_gn: int = 10, n_cg: int = 20, cg_rtol: float = 0.0, cg_max: int = 4000,
                  huber_delta: float = 1.345, d_near: float = 0.4, d_far: float = 10.0, grad_gate: float = 6.0,
                  sigma_photo: float = 1.0, r_floor: float = 1e-6, K=None, tiles=(0, 0), solver_threads: int = 0,
-                 cooperative: bool = False, stream=None):
+                 cooperative: bool = False, cg_variant: str = "auto", stream=None):
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("Keyframe needs a GPU (the library has no CPU path)")

@@ -107,3 +107,19 @@ def test_manual_tiling_validated():
     assert kf.kf_workspace_bytes(cfg) == 0
     cfg.solver_tiles_x, cfg.solver_tiles_y = 1, 1      # 19200 px in one workgroup: too many per thread
     assert kf.kf_workspace_bytes(cfg) == 0
+
+
+def test_binding_keyword_surface():
+    """The torch convenience layer accepts every documented option (checked without a GPU)."""
+    import inspect
+    from paper_2207_12244_amd.kf import Keyframe
+    params = inspect.signature(Keyframe.__init__).parameters
+    for name in ("precision", "pattern", "n_samples", "n_gn", "n_cg", "cg_rtol", "cg_max", "huber_delta",
+                 "d_near", "d_far", "grad_gate", "sigma_photo", "r_floor", "K", "tiles", "solver_threads",
+                 "cooperative", "cg_variant", "stream"):
+        assert name in params, name
+    import ast
+    import os as _os
+    src = open(_os.path.join(ROOT, "paper_2207_12244_amd", "kf.py")).read()
+    ast.parse(src)
+    assert "cfg.cg_variant" in src
