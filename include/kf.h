@@ -175,6 +175,61 @@ kf_status kf_export_state(kf_ctx* ctx, void* x, void* rho, void* rho_var, int32_
 kf_status kf_import_state(kf_ctx* ctx, const void* x, const void* rho, const void* rho_var,
                           const double* tau);
 
+/* ------------------------------------------------------------------ batched form
+
+   A batch fuses one new frame into each of n keyframe contexts (the per-frame
+   update of Sec. II-B and II-C, unchanged) with three launches for the whole
+   batch: frame staging, stereo over the union of the keyframes' textured
+   pixels, and one persistent solver launch in which every keyframe's team of
+   workgroups runs concurrently with the others. Each keyframe keeps its own
+   tiling, so a member's results are bit-identical to kf_fuse_frame on it. */
+
+typedef struct kf_batch kf_batch;
+
+#define KF_BATCH_MAX_MEMBERS 256
+
+typedef struct {
+  void* stream;            /* hipStream_t; every member context must use this stream */
+  int32_t use_graph;       /* 1 (default): replay the launches from one captured HIP graph; 0: direct launches */
+  void* workspace;         /* device buffer of at least kf_batch_workspace_bytes bytes, 256-byte aligned */
+  size_t workspace_bytes;
+} kf_batch_config;
+
+/* Defaults: stream 0, use_graph 1, no workspace. */
+void kf_batch_config_default(kf_batch_config* cfg);
+
+/* Device bytes the batch of these n member contexts (host array) needs; 0 if invalid. */
+size_t kf_batch_workspace_bytes(kf_ctx* const* members, int32_t n);
+
+/* Binds n distinct contexts (1 <= n <= KF_BATCH_MAX_MEMBERS). Members must share
+   precision, pattern, n_samples, the solver workgroup size and CG variant, the
+   device and cfg->stream; they may differ in size, intrinsics, tiling and
+   iteration counts. Schedules the solver teams, uploads the static tables and
+   (use_graph) captures the graph; allocates two small pinned host buffers.
+   KF_ERR_ARG if the members are incompatible or a team cannot be co-resident.
+   Members must outlive the batch; they stay usable on their own between
+   batch calls. *out = NULL on error. */
+kf_status kf_batch_create(kf_ctx* const* members, int32_t n, const kf_batch_config* cfg, kf_batch** out);
+
+/* One frame for every member: images is a host array of n device uint8 images
+   (member i's H x W), poses a host array of n row-major 4 x 4 T_WC (n x 16
+   doubles). Every member needs a prior (kf_set_prior). Enqueues work only; the
+   results are read per member (kf_read_depth, kf_read_stats), which also
+   report device errors. Blocks the host only while the descriptor buffer it
+   reuses (that of the call before last) is still being uploaded. */
+kf_status kf_batch_fuse(kf_batch* batch, const uint8_t* const* images, const double* poses);
+
+/* Solver launch of the batch: workgroups, threads per workgroup, pixels per
+   thread, and the longest per-workgroup team queue. */
+kf_status kf_batch_layout(const kf_batch* batch, int32_t out[4]);
+
+/* Message of the last failure on the batch ("" if none). */
+const char* kf_batch_last_error(const kf_batch* batch);
+
+/* Waits for the batch's pending descriptor uploads and frees its host state
+   (not the workspace, not the members). NULL is allowed. */
+void kf_batch_destroy(kf_batch* batch);
+
 #ifdef __cplusplus
 }
 #endif

@@ -20,7 +20,7 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libkf.so")
 ARCH = os.environ.get("KF_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["kf_api.hip", "kf_prior.hip", "kf_stereo.hip", "kf_solve.hip"]
+SOURCES = ["kf_api.hip", "kf_batch.hip", "kf_prior.hip", "kf_stereo.hip", "kf_solve.hip"]
 
 COMMON = [
     f"--offload-arch={ARCH}",

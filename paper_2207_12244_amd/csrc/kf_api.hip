@@ -7,22 +7,6 @@
 
 #include "kf_internal.h"
 
-struct kf_ctx {
-  kf_config cfg;
-  kf::Tiling tiling;
-  kf::Layout lay;
-  hipStream_t stream;
-  int device;
-  uint32_t epoch;
-  uint32_t frame;
-  bool has_prior;
-  double T_wc0[16];
-  std::string err;
-  char* ws;
-  uint64_t timeout_ticks;
-  int stereo_blocks;
-  int coresident;      // workgroups of the solver tiling the device holds at once (-1: not checked)
-};
 
 namespace kf {
 
@@ -212,13 +196,6 @@ bool inv4(const double* m, double* out) {
   return true;
 }
 
-bool pose_ok(const double* T) {
-  if (!T) return false;
-  for (int i = 0; i < 16; ++i)
-    if (!std::isfinite(T[i])) return false;
-  return T[12] == 0.0 && T[13] == 0.0 && T[14] == 0.0 && T[15] == 1.0;
-}
-
 // Epipolar constants of the photometric error (Sec. II-B): [R|t] = T_WC1^-1 T_WC0,
 // H = K R K^-1, b = K t, keyframe epipole K (-R^T t).
 bool frame_constants(const kf_ctx* c, const double* T1, FrameConst* fc) {
@@ -272,6 +249,85 @@ bool frame_constants(const kf_ctx* c, const double* T1, FrameConst* fc) {
   fc->sigma_photo = g.sigma_photo;
   return true;
 }
+
+}  // namespace
+
+namespace kf {
+
+bool pose_ok(const double* T) {
+  if (!T) return false;
+  for (int i = 0; i < 16; ++i)
+    if (!std::isfinite(T[i])) return false;
+  return T[12] == 0.0 && T[13] == 0.0 && T[14] == 0.0 && T[15] == 1.0;
+}
+
+bool stereo_args(kf_ctx* c, const uint8_t* image1, const double* T_wc1, StereoArgs* a) {
+  if (!frame_constants(c, T_wc1, &a->fc)) return false;
+  a->W = c->cfg.width;
+  a->H = c->cfg.height;
+  a->i0 = c->ws + c->lay.i0;
+  a->i1 = image1;
+  a->i1s = ws_ptr<uint8_t>(c, c->lay.i1s);
+  a->i1_stride = stage_stride(c->cfg.width);
+  a->list = ws_ptr<int32_t>(c, c->lay.list);
+  a->scal_ro = scal_ptr(c);
+  a->scal = scal_ptr(c);
+  a->rho = c->ws + c->lay.rho;
+  a->var = c->ws + c->lay.var;
+  a->match = ws_ptr<int32_t>(c, c->lay.match);
+  return true;
+}
+
+// Epochs one solver launch may consume: per GN iteration at most 2 per CG
+// iteration plus the initial and the scale synchronisation, plus slack.
+uint32_t solve_epoch_bound(const kf_config& g) {
+  const uint64_t limit = g.cg_rtol > 0.0 ? (uint64_t)g.cg_max : (uint64_t)g.n_cg;
+  return (uint32_t)((uint64_t)g.n_gn * (2 * limit + 2) + 2);
+}
+
+bool solve_pipelined(const kf_config& g) { return g.cg_variant == 2 || (g.cg_variant == 0 && g.cg_rtol == 0.0); }
+
+void solve_args(kf_ctx* c, SolveArgs* a) {
+  const kf_config& g = c->cfg;
+  const uint32_t bound = solve_epoch_bound(g);
+  a->W = g.width;
+  a->H = g.height;
+  a->tiles_x = c->tiling.tiles_x;
+  a->tiles_y = c->tiling.tiles_y;
+  a->tile_w = c->tiling.tile_w;
+  a->tile_h = c->tiling.tile_h;
+  a->prior = c->ws + c->lay.prior;
+  a->rho = c->ws + c->lay.rho;
+  a->var = c->ws + c->lay.var;
+  a->x = c->ws + c->lay.x;
+  a->scal = scal_ptr(c);
+  a->parts = ws_ptr<uint64_t>(c, c->lay.parts);
+  a->halo = ws_ptr<uint64_t>(c, c->lay.halo);
+  a->perim = 2 * c->tiling.tile_w + 2 * c->tiling.tile_h;
+  a->epoch_span = bound;
+  a->packed = (g.precision != KF_F64 && bound < 30000) ? 1 : 0;
+  a->n_gn = g.n_gn;
+  a->n_cg = g.n_cg;
+  a->cg_max = g.cg_max;
+  a->cg_rtol = g.cg_rtol;
+  a->huber_delta = g.huber_delta;
+  a->r_floor = g.r_floor;
+  a->timeout_ticks = c->timeout_ticks;
+}
+
+// c->epoch mirrors the device-side base (both advance by `bound` per launch);
+// before the 32-bit epochs could wrap, clear the exchange words and restart at 1.
+hipError_t epoch_wrap_if_needed(kf_ctx* c, uint32_t bound) {
+  if ((uint64_t)c->epoch + bound < 0xfff00000ull) return hipSuccess;
+  hipError_t e = launch_zero(c->ws + c->lay.parts, c->lay.total - c->lay.parts, c->stream);
+  if (e == hipSuccess) e = launch_set_u32(&scal_ptr(c)->epoch, 1u, c->stream);
+  if (e == hipSuccess) c->epoch = 1;
+  return e;
+}
+
+}  // namespace kf
+
+namespace {
 
 kf_status check_device_flags(kf_ctx* c) {
   DevScalars h;
@@ -414,19 +470,7 @@ kf_status kf_stereo_update(kf_ctx* c, const uint8_t* image1, const double T_wc1[
   if (!image1) return fail(c, KF_ERR_ARG, "kf_stereo_update: NULL image");
   if (!pose_ok(T_wc1)) return fail(c, KF_ERR_ARG, "kf_stereo_update: pose must be finite with last row 0 0 0 1");
   StereoArgs a;
-  if (!frame_constants(c, T_wc1, &a.fc)) return fail(c, KF_ERR_ARG, "kf_stereo_update: singular pose");
-  a.W = c->cfg.width;
-  a.H = c->cfg.height;
-  a.i0 = c->ws + c->lay.i0;
-  a.i1 = image1;
-  a.i1s = ws_ptr<uint8_t>(c, c->lay.i1s);
-  a.i1_stride = stage_stride(c->cfg.width);
-  a.list = ws_ptr<int32_t>(c, c->lay.list);
-  a.scal_ro = scal_ptr(c);
-  a.scal = scal_ptr(c);
-  a.rho = c->ws + c->lay.rho;
-  a.var = c->ws + c->lay.var;
-  a.match = ws_ptr<int32_t>(c, c->lay.match);
+  if (!stereo_args(c, image1, T_wc1, &a)) return fail(c, KF_ERR_ARG, "kf_stereo_update: singular pose");
   hipError_t e = launch_zero(&scal_ptr(c)->n_updated, sizeof(int32_t), c->stream);
   if (e == hipSuccess)
     e = launch_stereo(c->cfg.precision, c->cfg.pattern, c->cfg.n_samples, a, c->stereo_blocks, c->stream);
@@ -439,48 +483,19 @@ kf_status kf_solve(kf_ctx* c) {
   if (!c) return KF_ERR_ARG;
   if (!c->has_prior) return fail(c, KF_ERR_STATE, "kf_solve before kf_set_prior");
   const kf_config& g = c->cfg;
-  const uint64_t limit = g.cg_rtol > 0.0 ? (uint64_t)g.cg_max : (uint64_t)g.n_cg;
-  const uint64_t bound = (uint64_t)g.n_gn * (2 * limit + 2) + 2;
-  // c->epoch mirrors the device-side base (both advance by `bound` per launch);
-  // before the 32-bit epochs could wrap, clear the exchange words and restart at 1
-  if ((uint64_t)c->epoch + bound >= 0xfff00000ull) {
-    hipError_t e = launch_zero(c->ws + c->lay.parts, c->lay.total - c->lay.parts, c->stream);
-    if (e == hipSuccess) e = launch_set_u32(&scal_ptr(c)->epoch, 1u, c->stream);
-    if (e != hipSuccess) return hip_fail(c, e, "kf_solve (epoch wrap)");
-    c->epoch = 1;
-  }
+  const uint32_t bound = solve_epoch_bound(g);
+  hipError_t e = epoch_wrap_if_needed(c, bound);
+  if (e != hipSuccess) return hip_fail(c, e, "kf_solve (epoch wrap)");
   SolveArgs a;
-  a.W = g.width;
-  a.H = g.height;
-  a.tiles_x = c->tiling.tiles_x;
-  a.tiles_y = c->tiling.tiles_y;
-  a.tile_w = c->tiling.tile_w;
-  a.tile_h = c->tiling.tile_h;
-  a.prior = c->ws + c->lay.prior;
-  a.rho = c->ws + c->lay.rho;
-  a.var = c->ws + c->lay.var;
-  a.x = c->ws + c->lay.x;
-  a.scal = scal_ptr(c);
-  a.parts = ws_ptr<uint64_t>(c, c->lay.parts);
-  a.halo = ws_ptr<uint64_t>(c, c->lay.halo);
-  a.perim = 2 * c->tiling.tile_w + 2 * c->tiling.tile_h;
-  a.epoch_span = (uint32_t)bound;
-  a.packed = (g.precision != KF_F64 && bound < 30000) ? 1 : 0;
-  a.n_gn = g.n_gn;
-  a.n_cg = g.n_cg;
-  a.cg_max = g.cg_max;
-  a.cg_rtol = g.cg_rtol;
-  a.huber_delta = g.huber_delta;
-  a.r_floor = g.r_floor;
-  a.timeout_ticks = c->timeout_ticks;
-  const bool pipelined = g.cg_variant == 2 || (g.cg_variant == 0 && g.cg_rtol == 0.0);
+  solve_args(c, &a);
+  const bool pipelined = solve_pipelined(g);
   if (c->coresident < 0) c->coresident = solve_max_coresident(g.precision, c->tiling, pipelined, c->device);
   if (c->coresident < c->tiling.blocks)
     return fail(c, KF_ERR_ARG, "solver tiling needs " + std::to_string(c->tiling.blocks) +
                                " co-resident workgroups, the device holds " + std::to_string(c->coresident));
-  hipError_t e = launch_solve(g.precision, c->tiling, a, g.solver_cooperative != 0, pipelined, c->stream);
+  e = launch_solve(g.precision, c->tiling, a, g.solver_cooperative != 0, pipelined, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "kf_solve");
-  c->epoch += (uint32_t)bound;
+  c->epoch += bound;
   return KF_OK;
 }
 

@@ -1,0 +1,325 @@
+// Batched executor: many keyframe contexts, each fused with one new frame, by
+// one staging, one stereo and one persistent solver launch per call. The
+// per-keyframe arguments live in device tables; the per-frame part (image
+// pointer and epipolar constants) is uploaded from double-buffered pinned host
+// memory, and the three launches are replayed from one captured HIP graph.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kf_internal.h"
+
+using namespace kf;
+
+struct kf_batch {
+  std::vector<kf_ctx*> m;
+  hipStream_t stream = nullptr;
+  hipStream_t capture = nullptr;   // private stream the graph is captured on
+  int device = 0;
+  int prec = 0, pattern = 0, ns = 0, threads = 0, ppt = 0;
+  bool pipelined = false;
+  size_t smem = 0;
+  int grid = 0;                    // solver workgroups
+  int max_queue = 0;               // longest per-workgroup queue
+  int capacity = 0;                // co-resident workgroups of the batched solver
+  int stereo_blocks = 0;
+  bool use_graph = true;
+  StereoArgs* d_st = nullptr;
+  SolveArgs* d_so = nullptr;
+  int32_t* d_queue = nullptr;
+  int32_t* d_qoff = nullptr;
+  StereoArgs* h_pin[2] = {nullptr, nullptr};
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  bool ev_used[2] = {false, false};
+  int parity = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<int32_t> queue, qoff;
+  std::string err;
+
+  ~kf_batch() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    for (int i = 0; i < 2; ++i) {
+      if (ev[i]) {
+        (void)hipEventSynchronize(ev[i]);
+        (void)hipEventDestroy(ev[i]);
+      }
+      if (h_pin[i]) (void)hipHostFree(h_pin[i]);
+    }
+    if (capture) (void)hipStreamDestroy(capture);
+  }
+};
+
+namespace {
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+kf_status bfail(kf_batch* b, kf_status s, const std::string& msg) {
+  if (b) b->err = msg;
+  return s;
+}
+
+kf_status bhip(kf_batch* b, hipError_t e, const char* where) {
+  return bfail(b, KF_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+int total_members(kf_ctx* const* m, int n) {
+  int s = 0;
+  for (int i = 0; i < n; ++i) s += m[i]->tiling.blocks;
+  return s;
+}
+
+struct WsLayout {
+  size_t st, so, queue, qoff, total;
+};
+
+WsLayout ws_layout(int n, int members) {
+  WsLayout L;
+  size_t off = 0;
+  L.st = off; off += align256((size_t)n * sizeof(StereoArgs));
+  L.so = off; off += align256((size_t)n * sizeof(SolveArgs));
+  L.queue = off; off += align256((size_t)members * 4);
+  L.qoff = off; off += align256((size_t)(members + 1) * 4);
+  L.total = off;
+  return L;
+}
+
+// Estimated duration of one keyframe's solve (arbitrary units): per
+// synchronisation the team's polling cost plus its tile's stencil work, the
+// same latency model as the single-keyframe tiling choice.
+double team_cost(const kf_ctx* c) {
+  const kf_config& g = c->cfg;
+  const Tiling& t = c->tiling;
+  const double per_sync = 1.1 + 0.0065 * t.blocks + (double)t.tile_w * t.tile_h * 30.0 / 64.0 / 2400.0 *
+                                                        (t.threads == 256 ? 2.0 : 1.4);
+  const double cg = g.cg_rtol > 0.0 ? (double)g.cg_max : (double)g.n_cg;
+  return g.n_gn * (cg + 2.0) * per_sync;
+}
+
+// List schedule of the teams over `grid` workgroups: teams in order of
+// decreasing cost, each on the members that become free first (ties to the
+// lower workgroup index, which spreads a team evenly over the XCDs because
+// consecutive workgroups of a launch are dispatched to consecutive XCDs).
+// Every workgroup's queue follows the one global team order.
+void schedule(kf_batch* b) {
+  const int n = (int)b->m.size();
+  std::vector<int> order(n);
+  std::vector<double> cost(n);
+  for (int i = 0; i < n; ++i) {
+    order[i] = i;
+    cost[i] = team_cost(b->m[i]);
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+  std::vector<double> avail(b->grid, 0.0);
+  std::vector<std::vector<int32_t>> q(b->grid);
+  std::vector<int> idx(b->grid);
+  for (int c : order) {
+    const int B = b->m[c]->tiling.blocks;
+    for (int g = 0; g < b->grid; ++g) idx[g] = g;
+    std::partial_sort(idx.begin(), idx.begin() + B, idx.end(), [&](int x, int y) {
+      return avail[x] < avail[y] || (avail[x] == avail[y] && x < y);
+    });
+    std::sort(idx.begin(), idx.begin() + B);
+    double start = 0.0;
+    for (int k = 0; k < B; ++k) start = std::max(start, avail[idx[k]]);
+    for (int k = 0; k < B; ++k) {
+      avail[idx[k]] = start + cost[c];
+      q[idx[k]].push_back((int32_t)((c << 8) | k));
+    }
+  }
+  b->queue.clear();
+  b->qoff.assign(1, 0);
+  b->max_queue = 0;
+  for (int g = 0; g < b->grid; ++g) {
+    b->queue.insert(b->queue.end(), q[g].begin(), q[g].end());
+    b->qoff.push_back((int32_t)b->queue.size());
+    b->max_queue = std::max(b->max_queue, (int)q[g].size());
+  }
+}
+
+hipError_t enqueue_frame(kf_batch* b, hipStream_t s) {
+  const int n = (int)b->m.size();
+  hipError_t e = launch_stereo_batch(b->prec, b->pattern, b->ns, b->d_st, n, b->stereo_blocks, s);
+  if (e != hipSuccess) return e;
+  return launch_solve_batch(b->prec, b->threads, b->ppt, b->pipelined, b->d_so, b->d_queue, b->d_qoff, b->grid,
+                            b->smem, s);
+}
+
+hipError_t build_graph(kf_batch* b) {
+  hipError_t e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  hipError_t el = enqueue_frame(b, b->capture);
+  e = hipStreamEndCapture(b->capture, &b->graph);
+  if (el != hipSuccess) return el;
+  if (e != hipSuccess) return e;
+  return hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+}
+
+}  // namespace
+
+extern "C" {
+
+void kf_batch_config_default(kf_batch_config* cfg) {
+  if (!cfg) return;
+  std::memset(cfg, 0, sizeof(*cfg));
+  cfg->use_graph = 1;
+}
+
+size_t kf_batch_workspace_bytes(kf_ctx* const* members, int32_t n) {
+  if (!members || n < 1 || n > KF_BATCH_MAX) return 0;
+  for (int i = 0; i < n; ++i)
+    if (!members[i]) return 0;
+  return ws_layout(n, total_members(members, n)).total;
+}
+
+kf_status kf_batch_create(kf_ctx* const* members, int32_t n, const kf_batch_config* cfg, kf_batch** out) {
+  if (!out) return KF_ERR_ARG;
+  *out = nullptr;
+  if (!members || !cfg || n < 1 || n > KF_BATCH_MAX) return KF_ERR_ARG;
+  if (cfg->use_graph != 0 && cfg->use_graph != 1) return KF_ERR_ARG;
+  for (int i = 0; i < n; ++i) {
+    if (!members[i]) return KF_ERR_ARG;
+    for (int j = 0; j < i; ++j)
+      if (members[j] == members[i]) return KF_ERR_ARG;
+  }
+  const kf_ctx* c0 = members[0];
+  for (int i = 0; i < n; ++i) {
+    const kf_ctx* c = members[i];
+    if (c->cfg.precision != c0->cfg.precision || c->cfg.pattern != c0->cfg.pattern ||
+        c->cfg.n_samples != c0->cfg.n_samples || c->tiling.threads != c0->tiling.threads ||
+        solve_pipelined(c->cfg) != solve_pipelined(c0->cfg) || c->device != c0->device ||
+        c->stream != reinterpret_cast<hipStream_t>(cfg->stream))
+      return KF_ERR_ARG;
+  }
+  const int members_total = total_members(members, n);
+  const WsLayout L = ws_layout(n, members_total);
+  if (!cfg->workspace) return KF_ERR_ARG;
+  if (cfg->workspace_bytes < L.total) return KF_ERR_OOM;
+  if (reinterpret_cast<uintptr_t>(cfg->workspace) % 256 != 0) return KF_ERR_ARG;
+
+  kf_batch* b = new (std::nothrow) kf_batch();
+  if (!b) return KF_ERR_OOM;
+  b->m.assign(members, members + n);
+  b->stream = reinterpret_cast<hipStream_t>(cfg->stream);
+  b->device = c0->device;
+  b->prec = c0->cfg.precision;
+  b->pattern = c0->cfg.pattern;
+  b->ns = c0->cfg.n_samples;
+  b->threads = c0->tiling.threads;
+  b->pipelined = solve_pipelined(c0->cfg);
+  b->use_graph = cfg->use_graph != 0;
+  b->stereo_blocks = c0->stereo_blocks;
+  char* ws = reinterpret_cast<char*>(cfg->workspace);
+  b->d_st = reinterpret_cast<StereoArgs*>(ws + L.st);
+  b->d_so = reinterpret_cast<SolveArgs*>(ws + L.so);
+  b->d_queue = reinterpret_cast<int32_t*>(ws + L.queue);
+  b->d_qoff = reinterpret_cast<int32_t*>(ws + L.qoff);
+
+  int maxB = 0, maxw = 0, maxh = 0;
+  for (kf_ctx* c : b->m) {
+    b->ppt = std::max(b->ppt, c->tiling.ppt);
+    maxB = std::max(maxB, c->tiling.blocks);
+    maxw = std::max(maxw, c->tiling.tile_w);
+    maxh = std::max(maxh, c->tiling.tile_h);
+  }
+  if (!solve_batch_supported(b->prec, b->threads, b->ppt)) {
+    delete b;
+    return KF_ERR_ARG;
+  }
+  // LDS: room for the largest team's partials and the largest tile's rings
+  b->smem = solve_batch_smem_bytes(b->prec, b->threads, maxB, maxw, maxh);
+  b->capacity = solve_batch_coresident(b->prec, b->threads, b->ppt, b->pipelined, b->smem, b->device);
+  if (b->capacity < maxB) {
+    delete b;
+    return KF_ERR_ARG;
+  }
+  b->grid = std::min(b->capacity, members_total);
+  schedule(b);
+
+  std::vector<SolveArgs> so(n);
+  for (int i = 0; i < n; ++i) {
+    solve_args(b->m[i], &so[i]);
+    // a member may wait for its team while the team's other members finish
+    // the teams queued before it
+    so[i].timeout_ticks = b->m[i]->timeout_ticks * (uint64_t)b->max_queue;
+  }
+  hipError_t e = hipMemcpy(b->d_so, so.data(), n * sizeof(SolveArgs), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(b->d_queue, b->queue.data(), b->queue.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(b->d_qoff, b->qoff.data(), b->qoff.size() * 4, hipMemcpyHostToDevice);
+  for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+    e = hipHostMalloc(reinterpret_cast<void**>(&b->h_pin[i]), n * sizeof(StereoArgs), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev[i], hipEventDisableTiming);
+  }
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
+  if (e == hipSuccess && b->use_graph) e = build_graph(b);
+  if (e != hipSuccess) {
+    delete b;
+    return KF_ERR_HIP;
+  }
+  *out = b;
+  return KF_OK;
+}
+
+void kf_batch_destroy(kf_batch* b) { delete b; }
+
+const char* kf_batch_last_error(const kf_batch* b) {
+  if (!b) return "no batch";
+  return b->err.c_str();
+}
+
+kf_status kf_batch_layout(const kf_batch* b, int32_t out[4]) {
+  if (!b || !out) return KF_ERR_ARG;
+  out[0] = b->grid;
+  out[1] = b->threads;
+  out[2] = b->ppt;
+  out[3] = b->max_queue;
+  return KF_OK;
+}
+
+kf_status kf_batch_fuse(kf_batch* b, const uint8_t* const* images, const double* poses) {
+  if (!b) return KF_ERR_ARG;
+  if (!images || !poses) return bfail(b, KF_ERR_ARG, "kf_batch_fuse: NULL images or poses");
+  const int n = (int)b->m.size();
+  for (int i = 0; i < n; ++i) {
+    if (!b->m[i]->has_prior) return bfail(b, KF_ERR_STATE, "kf_batch_fuse: member " + std::to_string(i) +
+                                                            " has no prior (kf_set_prior)");
+    if (!images[i]) return bfail(b, KF_ERR_ARG, "kf_batch_fuse: NULL image for member " + std::to_string(i));
+    if (!pose_ok(poses + 16 * (size_t)i))
+      return bfail(b, KF_ERR_ARG, "kf_batch_fuse: pose of member " + std::to_string(i) +
+                                  " must be finite with last row 0 0 0 1");
+  }
+  // the pinned buffer of this parity was last read by the copy two calls ago
+  const int p = b->parity;
+  hipError_t e = hipSuccess;
+  if (b->ev_used[p]) {
+    e = hipEventSynchronize(b->ev[p]);
+    if (e != hipSuccess) return bhip(b, e, "kf_batch_fuse (descriptor buffer)");
+  }
+  StereoArgs* h = b->h_pin[p];
+  for (int i = 0; i < n; ++i)
+    if (!stereo_args(b->m[i], images[i], poses + 16 * (size_t)i, &h[i]))
+      return bfail(b, KF_ERR_ARG, "kf_batch_fuse: singular pose for member " + std::to_string(i));
+  for (kf_ctx* c : b->m) {
+    e = epoch_wrap_if_needed(c, solve_epoch_bound(c->cfg));
+    if (e != hipSuccess) return bhip(b, e, "kf_batch_fuse (epoch wrap)");
+  }
+  e = hipMemcpyAsync(b->d_st, h, n * sizeof(StereoArgs), hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) e = hipEventRecord(b->ev[p], b->stream);
+  if (e != hipSuccess) return bhip(b, e, "kf_batch_fuse (descriptor upload)");
+  b->ev_used[p] = true;
+  b->parity ^= 1;
+  e = b->use_graph ? hipGraphLaunch(b->exec, b->stream) : enqueue_frame(b, b->stream);
+  if (e != hipSuccess) return bhip(b, e, "kf_batch_fuse");
+  for (kf_ctx* c : b->m) {
+    ++c->frame;
+    c->epoch += solve_epoch_bound(c->cfg);
+  }
+  return KF_OK;
+}
+
+}  // extern "C"

@@ -5,6 +5,8 @@
 #include <stdint.h>
 #include <stddef.h>
 
+#include <string>
+
 #include "kf.h"
 
 namespace kf {
@@ -90,6 +92,7 @@ struct Tiling {
 constexpr int NV_MAX = 3;            // values reduced per synchronisation
 constexpr int MAX_TEAM = 256;        // workgroups per keyframe team
 constexpr int CHUNK = 256;           // pixels per compaction chunk
+#define KF_BATCH_MAX KF_BATCH_MAX_MEMBERS
 
 bool choose_tiling(int W, int H, int tx_req, int ty_req, int threads_req, int prec, Tiling* t);
 // Workgroups of this tiling the device can hold at once (0 if unknown).
@@ -169,13 +172,54 @@ struct ImportArgs {
 
 hipError_t launch_prior(int prec, const PriorArgs& a, hipStream_t s);
 hipError_t launch_stereo(int prec, int pattern, int ns, const StereoArgs& a, int blocks, hipStream_t s);
+hipError_t launch_stereo_batch(int prec, int pattern, int ns, const StereoArgs* tab, int n, int blocks,
+                               hipStream_t s);
 hipError_t launch_solve(int prec, const Tiling& t, const SolveArgs& a, bool cooperative, bool pipelined,
                         hipStream_t s);
+// Batched solver: workgroup g runs the team members queue[qoff[g] .. qoff[g+1])
+// in order, each entry (keyframe << 8) | member; all `grid` workgroups must be
+// co-resident.
+hipError_t launch_solve_batch(int prec, int threads, int ppt, bool pipelined, const SolveArgs* tab,
+                              const int32_t* queue, const int32_t* qoff, int grid, size_t smem, hipStream_t s);
+size_t solve_batch_smem_bytes(int prec, int threads, int team_blocks, int tile_w, int tile_h);
+int solve_batch_coresident(int prec, int threads, int ppt, bool pipelined, size_t smem, int device);
+bool solve_batch_supported(int prec, int threads, int ppt);
 hipError_t launch_read(int prec, const ReadArgs& a, hipStream_t s);
 hipError_t launch_import(int prec, const ImportArgs& a, hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_set_u32(uint32_t* p, uint32_t v, hipStream_t s);
 size_t solve_smem_bytes(int prec, const Tiling& t);
 int stereo_grid_blocks(int device);
+
+}  // namespace kf
+
+// Host state of one keyframe context (opaque to callers).
+struct kf_ctx {
+  kf_config cfg;
+  kf::Tiling tiling;
+  kf::Layout lay;
+  hipStream_t stream;
+  int device;
+  uint32_t epoch;      // host mirror of the device-side epoch base
+  uint32_t frame;
+  bool has_prior;
+  double T_wc0[16];
+  std::string err;
+  char* ws;
+  uint64_t timeout_ticks;
+  int stereo_blocks;
+  int coresident;      // workgroups of the solver tiling the device holds at once (-1: not checked)
+};
+
+namespace kf {
+
+// Shared by the single-keyframe calls and the batched executor, so that both
+// hand the kernels the same arguments.
+bool pose_ok(const double* T);
+bool stereo_args(kf_ctx* c, const uint8_t* image1, const double* T_wc1, StereoArgs* a);
+uint32_t solve_epoch_bound(const kf_config& g);
+bool solve_pipelined(const kf_config& g);
+void solve_args(kf_ctx* c, SolveArgs* a);
+hipError_t epoch_wrap_if_needed(kf_ctx* c, uint32_t bound);   // restart epochs before they could wrap
 
 }  // namespace kf

@@ -241,12 +241,12 @@ struct Team {
   }
 };
 
+// One member (tile b) of the team that solves keyframe `a`; every thread of
+// the workgroup calls it. LDS: `smem` as sized by smem_for for this team.
 template <typename T, int NT, int PPT, bool PIPE>
-__global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
+__device__ __forceinline__ void solve_member(const SolveArgs& a, const int b, unsigned char* smem) {
   constexpr int NW = NT / 64;
-  extern __shared__ __align__(16) unsigned char smem[];
   const int B = a.tiles_x * a.tiles_y;
-  const int b = blockIdx.x;
   const int tid = threadIdx.x;
   const int W = a.W, H = a.H, N = W * H;
 
@@ -611,6 +611,30 @@ __global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
   }
 }
 
+template <typename T, int NT, int PPT, bool PIPE>
+__global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  solve_member<T, NT, PPT, PIPE>(a, blockIdx.x, smem);
+}
+
+// Batched form: workgroup g works through its queue of (keyframe, member)
+// entries in order. Queues list teams in one global order, so the lowest
+// unfinished team always has every member at it and the launch cannot
+// deadlock, provided all workgroups are co-resident.
+template <typename T, int NT, int PPT, bool PIPE>
+__global__ __launch_bounds__(NT) void k_solve_batch(const SolveArgs* __restrict__ tab,
+                                                    const int32_t* __restrict__ queue,
+                                                    const int32_t* __restrict__ qoff) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int q1 = qoff[blockIdx.x + 1];
+  for (int q = qoff[blockIdx.x]; q < q1; ++q) {
+    const int32_t ent = queue[q];
+    const SolveArgs a = tab[ent >> 8];
+    __syncthreads();   // the previous member's last LDS reads are done
+    solve_member<T, NT, PPT, PIPE>(a, ent & 255, smem);
+  }
+}
+
 }  // namespace
 
 namespace {
@@ -636,6 +660,23 @@ const void* solve_fn_p(const Tiling& t) {
 template <typename T>
 const void* solve_fn(const Tiling& t, bool pipelined) {
   return pipelined ? solve_fn_p<T, true>(t) : solve_fn_p<T, false>(t);
+}
+
+template <typename T, bool PIPE>
+const void* batch_fn_p(int threads, int ppt) {
+#define KF_PPT(nt, n) if (threads == nt && ppt == n) return reinterpret_cast<const void*>(&k_solve_batch<T, nt, n, PIPE>);
+  KF_PPT(256, 1) KF_PPT(256, 2) KF_PPT(256, 3) KF_PPT(256, 4)
+  KF_PPT(512, 1) KF_PPT(512, 2)
+  if (sizeof(T) == 4) {
+    KF_PPT(256, 6) KF_PPT(512, 3)
+  }
+#undef KF_PPT
+  return nullptr;
+}
+
+const void* batch_fn(int prec, int threads, int ppt, bool pipelined) {
+  if (prec == KF_F64) return pipelined ? batch_fn_p<double, true>(threads, ppt) : batch_fn_p<double, false>(threads, ppt);
+  return pipelined ? batch_fn_p<float, true>(threads, ppt) : batch_fn_p<float, false>(threads, ppt);
 }
 
 template <typename T>
@@ -672,6 +713,36 @@ hipError_t launch_solve(int prec, const Tiling& t, const SolveArgs& a, bool coop
                         hipStream_t s) {
   if (prec == KF_F64) return solve_t<double>(t, a, cooperative, pipelined, s);
   return solve_t<float>(t, a, cooperative, pipelined, s);
+}
+
+size_t solve_batch_smem_bytes(int prec, int threads, int team_blocks, int tile_w, int tile_h) {
+  Tiling t{};
+  t.threads = threads;
+  t.blocks = team_blocks;
+  t.tile_w = tile_w;
+  t.tile_h = tile_h;
+  return smem_for(prec == KF_F64 ? 8 : 4, t);
+}
+
+bool solve_batch_supported(int prec, int threads, int ppt) { return batch_fn(prec, threads, ppt, true) != nullptr; }
+
+int solve_batch_coresident(int prec, int threads, int ppt, bool pipelined, size_t smem, int device) {
+  const void* fn = batch_fn(prec, threads, ppt, pipelined);
+  if (!fn) return 0;
+  if (smem > 48 * 1024 && hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess)
+    return 0;
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, smem) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
+  return per_cu * cus;
+}
+
+hipError_t launch_solve_batch(int prec, int threads, int ppt, bool pipelined, const SolveArgs* tab,
+                              const int32_t* queue, const int32_t* qoff, int grid, size_t smem, hipStream_t s) {
+  const void* fn = batch_fn(prec, threads, ppt, pipelined);
+  if (!fn || grid < 1) return hipErrorInvalidValue;
+  void* args[] = {const_cast<SolveArgs**>(&tab), const_cast<int32_t**>(&queue), const_cast<int32_t**>(&qoff)};
+  return hipLaunchKernel(fn, dim3(grid), dim3(threads), args, (unsigned)smem, s);
 }
 
 }  // namespace kf

@@ -208,203 +208,267 @@ __device__ inline double readlane_t(double v, int src) {
 template <typename T>
 __device__ inline T shfl_t(T v, int src) { return __shfl(v, src, 64); }
 
+// One textured pixel (entry `idx` of the search list of keyframe `a`) for the
+// lane group of this thread. Every lane of the wavefront calls it together
+// (cross-lane operations inside); `active` masks groups without an entry.
+// Returns true if the group's lane 0 wrote a new filter estimate.
 template <typename T, typename TI, int PAT, int NS>
-__global__ __launch_bounds__(ST_THREADS) void k_stereo(StereoArgs a) {
+__device__ inline bool stereo_pixel(const StereoArgs& a, int idx, bool active, int lane) {
   constexpr int G = NS < 64 ? NS : 64;    // lanes per pixel
   constexpr int S = NS / G;                // samples per lane
-  constexpr int GPW = 64 / G;              // pixels per wavefront
   constexpr int P = PAT == KF_PAT_LINE5 ? 5 : 25;
   constexpr T INF = (T)INFINITY;
-
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
   const int grp = lane / G;
   const int gl = lane % G;
-  const int count = a.scal_ro->mask_count;
-  const int groups_per_block = ST_WAVES * GPW;
-  const int ngroups = gridDim.x * groups_per_block;
-  const int my_group = blockIdx.x * groups_per_block + wave * GPW + grp;
-  const int rounds = (count + ngroups - 1) / ngroups;
   const TI* i0 = static_cast<const TI*>(a.i0);
   T* rho_s = static_cast<T*>(a.rho);
   T* var_s = static_cast<T*>(a.var);
   const int W = a.W, H = a.H;
   const int st = a.i1_stride;
-  int updated_here = 0;
+  bool updated = false;
+  const int pix = active ? a.list[idx] : 0;
+  const T u = (T)(pix % W), v = (T)(pix / W);
+  const T rho0 = rho_s[pix], var0 = var_s[pix];
+  const bool has = var0 > (T)0;
+  PixelGeom<T> g = pixel_geometry<T, PAT, NS>(a, u, v, rho0, var0, has);
+  g.ok = g.ok && active;
 
-  for (int r = 0; r < rounds; ++r) {      // wave-uniform trip count (cross-lane shuffles below)
-    const int idx = my_group + r * ngroups;
-    const bool active = idx < count;
-    const int pix = active ? a.list[idx] : 0;
-    const T u = (T)(pix % W), v = (T)(pix / W);
-    const T rho0 = rho_s[pix], var0 = var_s[pix];
-    const bool has = var0 > (T)0;
-    PixelGeom<T> g = pixel_geometry<T, PAT, NS>(a, u, v, rho0, var0, has);
-    g.ok = g.ok && active;
+  // keyframe pattern I0(a_j) (in the form's patch storage type): with at least
+  // P lanes per pixel, lane j evaluates point j and every lane receives all P
+  // values by a cross-lane broadcast (a scalar readlane when one pixel fills
+  // the wavefront); with fewer lanes every lane evaluates all points.
+  T mine = (T)0;
+  T pat[P];
+  if (G >= P) {
+    if (gl < P && active) mine = kf_point<T, TI, PAT>(i0, W, H, u, v, g, gl);
+#pragma unroll
+    for (int j = 0; j < P; ++j) pat[j] = (G == 64) ? readlane_t(mine, j) : shfl_t(mine, grp * G + j);
+  } else {
+#pragma unroll
+    for (int j = 0; j < P; ++j) pat[j] = active ? kf_point<T, TI, PAT>(i0, W, H, u, v, g, j) : (T)0;
+  }
 
-    // keyframe pattern I0(a_j) (in the form's patch storage type): with at least
-    // P lanes per pixel, lane j evaluates point j and every lane receives all P
-    // values by a cross-lane broadcast (a scalar readlane when one pixel fills
-    // the wavefront); with fewer lanes every lane evaluates all points.
-    T mine = (T)0;
-    T pat[P];
-    if (G >= P) {
-      if (gl < P && active) mine = kf_point<T, TI, PAT>(i0, W, H, u, v, g, gl);
+  // SSD of this lane's samples
+  T ssd[S];
+  T best = INF;
+  int bestk = 0x7fffffff;
 #pragma unroll
-      for (int j = 0; j < P; ++j) pat[j] = (G == 64) ? readlane_t(mine, j) : shfl_t(mine, grp * G + j);
-    } else {
+  for (int s = 0; s < S; ++s) {
+    const int k = gl + G * s;
+    T px, py, rk;
+    sample_pos<T, NS>(g, a.fc, k, px, py, rk);
+    bool ok = g.ok && isfinite((double)rk) && rk >= (T)a.fc.rho_min && rk <= (T)a.fc.rho_max;
+    T acc = (T)0;
+    if (PAT == KF_PAT_LINE5) {
 #pragma unroll
-      for (int j = 0; j < P; ++j) pat[j] = active ? kf_point<T, TI, PAT>(i0, W, H, u, v, g, j) : (T)0;
-    }
-
-    // SSD of this lane's samples
-    T ssd[S];
-    T best = INF;
-    int bestk = 0x7fffffff;
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      const int k = gl + G * s;
-      T px, py, rk;
-      sample_pos<T, NS>(g, a.fc, k, px, py, rk);
-      bool ok = g.ok && isfinite((double)rk) && rk >= (T)a.fc.rho_min && rk <= (T)a.fc.rho_max;
-      T acc = (T)0;
-      if (PAT == KF_PAT_LINE5) {
+      for (int j = 0; j < 5; ++j) {
+        const T jj = (T)(j - 2);
+        ok = ok && inside<T>(px + jj * g.lx, py + jj * g.ly, W, H);
+      }
+      if (ok) {
 #pragma unroll
         for (int j = 0; j < 5; ++j) {
-          const T jj = (T)(j - 2);
-          ok = ok && inside<T>(px + jj * g.lx, py + jj * g.ly, W, H);
+          const T e = point_residual<T, PAT>(a, g, px, py, j, pat[j]);
+          acc += e * e;
         }
-        if (ok) {
+      }
+    } else {
+      ok = ok && px - (T)2 >= (T)0 && px + (T)2 <= (T)(W - 1) && py - (T)2 >= (T)0 &&
+           py + (T)2 <= (T)(H - 1);
+      if (ok) {
+        // 6 x 6 tap window shared by the 25 points (translation-only warp)
+        const T fpx = floor(px), fpy = floor(py);
+        const T f = px - fpx, gg = py - fpy;
+        const int c0 = (int)fpx - 2, r0 = (int)fpy - 2;
+        T hprev[5];
+        const uint8_t* base = a.i1s + (size_t)r0 * st + c0;
 #pragma unroll
-          for (int j = 0; j < 5; ++j) {
-            const T e = point_residual<T, PAT>(a, g, px, py, j, pat[j]);
-            acc += e * e;
-          }
-        }
-      } else {
-        ok = ok && px - (T)2 >= (T)0 && px + (T)2 <= (T)(W - 1) && py - (T)2 >= (T)0 &&
-             py + (T)2 <= (T)(H - 1);
-        if (ok) {
-          // 6 x 6 tap window shared by the 25 points (translation-only warp)
-          const T fpx = floor(px), fpy = floor(py);
-          const T f = px - fpx, gg = py - fpy;
-          const int c0 = (int)fpx - 2, r0 = (int)fpy - 2;
-          T hprev[5];
-          const uint8_t* base = a.i1s + (size_t)r0 * st + c0;
+        for (int n = 0; n < 6; ++n) {
+          // rows and the 6th column may reach one pad row / byte (weight 0 there)
+          T t[6];
+          taps6<T>(base + (size_t)n * st, t);
+          T hrow[5];
 #pragma unroll
-          for (int n = 0; n < 6; ++n) {
-            // rows and the 6th column may reach one pad row / byte (weight 0 there)
-            T t[6];
-            taps6<T>(base + (size_t)n * st, t);
-            T hrow[5];
+          for (int m = 0; m < 5; ++m) hrow[m] = t[m] + f * (t[m + 1] - t[m]);
+          if (n > 0) {
 #pragma unroll
-            for (int m = 0; m < 5; ++m) hrow[m] = t[m] + f * (t[m + 1] - t[m]);
-            if (n > 0) {
-#pragma unroll
-              for (int m = 0; m < 5; ++m) {
-                const T val = hprev[m] + gg * (hrow[m] - hprev[m]);
-                const T e = val - pat[(n - 1) * 5 + m];
-                acc += e * e;
-              }
+            for (int m = 0; m < 5; ++m) {
+              const T val = hprev[m] + gg * (hrow[m] - hprev[m]);
+              const T e = val - pat[(n - 1) * 5 + m];
+              acc += e * e;
             }
-#pragma unroll
-            for (int m = 0; m < 5; ++m) hprev[m] = hrow[m];
           }
+#pragma unroll
+          for (int m = 0; m < 5; ++m) hprev[m] = hrow[m];
         }
       }
-      ssd[s] = ok ? acc : INF;
-      if (ssd[s] < best) {          // s increases with k: keeps the first minimum
-        best = ssd[s];
-        bestk = k;
-      }
     }
-    // argmin across the group: smaller SSD, ties -> smaller k
+    ssd[s] = ok ? acc : INF;
+    if (ssd[s] < best) {          // s increases with k: keeps the first minimum
+      best = ssd[s];
+      bestk = k;
+    }
+  }
+  // argmin across the group: smaller SSD, ties -> smaller k
 #pragma unroll
-    for (int m = 1; m < G; m <<= 1) {
-      const T ob = shfl_xor_t(best, m);
-      const int ok_ = __shfl_xor(bestk, m, 64);
-      if (ob < best || (ob == best && ok_ < bestk)) {
-        best = ob;
-        bestk = ok_;
-      }
+  for (int m = 1; m < G; m <<= 1) {
+    const T ob = shfl_xor_t(best, m);
+    const int ok_ = __shfl_xor(bestk, m, 64);
+    if (ob < best || (ob == best && ok_ < bestk)) {
+      best = ob;
+      bestk = ok_;
     }
-    const bool any_valid = g.ok && best < INF;
-    const int kstar = bestk;
-    // SSD of the two neighbours k* - 1 and k* + 1
-    T s_m = INF, s_p = INF;
-    {
-      const int km = any_valid ? kstar - 1 : -1;
-      const int kp = any_valid ? kstar + 1 : NS;
-      const int base = grp * G;
-      T vm = INF, vp = INF;
-      // every lane reads its own slot value for the owner's sample index
-      const int slot_m = km >= 0 ? km / G : 0, slot_p = kp < NS ? kp / G : 0;
-      T mine_m = ssd[0], mine_p = ssd[0];
+  }
+  const bool any_valid = g.ok && best < INF;
+  const int kstar = bestk;
+  // SSD of the two neighbours k* - 1 and k* + 1
+  T s_m = INF, s_p = INF;
+  {
+    const int km = any_valid ? kstar - 1 : -1;
+    const int kp = any_valid ? kstar + 1 : NS;
+    const int base = grp * G;
+    T vm = INF, vp = INF;
+    // every lane reads its own slot value for the owner's sample index
+    const int slot_m = km >= 0 ? km / G : 0, slot_p = kp < NS ? kp / G : 0;
+    T mine_m = ssd[0], mine_p = ssd[0];
 #pragma unroll
-      for (int s = 1; s < S; ++s) {
-        if (slot_m == s) mine_m = ssd[s];
-        if (slot_p == s) mine_p = ssd[s];
-      }
-      vm = shfl_t(mine_m, base + (km >= 0 ? km % G : 0));
-      vp = shfl_t(mine_p, base + (kp < NS ? kp % G : 0));
-      s_m = km >= 0 ? vm : INF;
-      s_p = kp < NS ? vp : INF;
+    for (int s = 1; s < S; ++s) {
+      if (slot_m == s) mine_m = ssd[s];
+      if (slot_p == s) mine_p = ssd[s];
     }
-    const bool has_nb = any_valid && (s_m < INF || s_p < INF);
-    const int nstar = (s_m <= s_p) ? kstar - 1 : kstar + 1;
+    vm = shfl_t(mine_m, base + (km >= 0 ? km % G : 0));
+    vp = shfl_t(mine_p, base + (kp < NS ? kp % G : 0));
+    s_m = km >= 0 ? vm : INF;
+    s_p = kp < NS ? vp : INF;
+  }
+  const bool has_nb = any_valid && (s_m < INF || s_p < INF);
+  const int nstar = (s_m <= s_p) ? kstar - 1 : kstar + 1;
 
-    // residual vectors at k* and n*: lane j of the group computes point j
-    T pxk = 0, pyk = 0, rk_k = 0, pxn = 0, pyn = 0, rk_n = 0;
-    if (has_nb) {
-      sample_pos<T, NS>(g, a.fc, kstar, pxk, pyk, rk_k);
-      sample_pos<T, NS>(g, a.fc, nstar, pxn, pyn, rk_n);
+  // residual vectors at k* and n*: lane j of the group computes point j
+  T pxk = 0, pyk = 0, rk_k = 0, pxn = 0, pyn = 0, rk_n = 0;
+  if (has_nb) {
+    sample_pos<T, NS>(g, a.fc, kstar, pxk, pyk, rk_k);
+    sample_pos<T, NS>(g, a.fc, nstar, pxn, pyn, rk_n);
+  }
+  T sum_kd = 0, sum_dd = 0;
+  if (has_nb) {
+    for (int j = gl; j < P; j += G) {
+      const T pj = G >= P ? mine : kf_point<T, TI, PAT>(i0, W, H, u, v, g, j);
+      const T ek = point_residual<T, PAT>(a, g, pxk, pyk, j, pj);
+      const T en = point_residual<T, PAT>(a, g, pxn, pyn, j, pj);
+      const T de = en - ek;
+      sum_kd += ek * de;
+      sum_dd += de * de;
     }
-    T sum_kd = 0, sum_dd = 0;
-    if (has_nb) {
-      for (int j = gl; j < P; j += G) {
-        const T pj = G >= P ? mine : kf_point<T, TI, PAT>(i0, W, H, u, v, g, j);
-        const T ek = point_residual<T, PAT>(a, g, pxk, pyk, j, pj);
-        const T en = point_residual<T, PAT>(a, g, pxn, pyn, j, pj);
-        const T de = en - ek;
-        sum_kd += ek * de;
-        sum_dd += de * de;
-      }
-    }
+  }
 #pragma unroll
-    for (int m = 1; m < G; m <<= 1) {
-      sum_kd += shfl_xor_t(sum_kd, m);
-      sum_dd += shfl_xor_t(sum_dd, m);
-    }
-    if (gl == 0 && active) {
-      a.match[pix] = (g.ok && best < INF) ? kstar : -1;
-      if (has_nb && sum_dd > (T)0) {
-        T lam = -sum_kd / sum_dd;
-        lam = lam < (T)0 ? (T)0 : (lam > (T)1 ? (T)1 : lam);
-        const T d_a = (T)1 / rk_k, d_b = (T)1 / rk_n;
-        const T dd = d_b - d_a;
-        const T dstar = d_a + lam * dd;
-        const T sp = (T)a.fc.sigma_photo;
-        const T var_d = sp * sp * dd * dd / sum_dd;       // eq. (semi) with J = de / dd
-        const T ro = (T)1 / dstar;
-        const T d2 = dstar * dstar;
-        const T vo = var_d / (d2 * d2);
-        if (isfinite((double)var_d) && var_d > (T)0 && isfinite((double)dstar) && dstar > (T)0 &&
-            isfinite((double)vo) && vo > (T)0) {
-          if (has) {   // Gaussian product with the current estimate
-            rho_s[pix] = (vo * rho0 + var0 * ro) / (var0 + vo);
-            var_s[pix] = var0 * vo / (var0 + vo);
-          } else {
-            rho_s[pix] = ro;
-            var_s[pix] = vo;
-          }
-          ++updated_here;
+  for (int m = 1; m < G; m <<= 1) {
+    sum_kd += shfl_xor_t(sum_kd, m);
+    sum_dd += shfl_xor_t(sum_dd, m);
+  }
+  if (gl == 0 && active) {
+    a.match[pix] = (g.ok && best < INF) ? kstar : -1;
+    if (has_nb && sum_dd > (T)0) {
+      T lam = -sum_kd / sum_dd;
+      lam = lam < (T)0 ? (T)0 : (lam > (T)1 ? (T)1 : lam);
+      const T d_a = (T)1 / rk_k, d_b = (T)1 / rk_n;
+      const T dd = d_b - d_a;
+      const T dstar = d_a + lam * dd;
+      const T sp = (T)a.fc.sigma_photo;
+      const T var_d = sp * sp * dd * dd / sum_dd;       // eq. (semi) with J = de / dd
+      const T ro = (T)1 / dstar;
+      const T d2 = dstar * dstar;
+      const T vo = var_d / (d2 * d2);
+      if (isfinite((double)var_d) && var_d > (T)0 && isfinite((double)dstar) && dstar > (T)0 &&
+          isfinite((double)vo) && vo > (T)0) {
+        if (has) {   // Gaussian product with the current estimate
+          rho_s[pix] = (vo * rho0 + var0 * ro) / (var0 + vo);
+          var_s[pix] = var0 * vo / (var0 + vo);
+        } else {
+          rho_s[pix] = ro;
+          var_s[pix] = vo;
         }
+        updated = true;
       }
     }
+  }
+  return updated;
+}
+
+template <typename T, typename TI, int PAT, int NS>
+__global__ __launch_bounds__(ST_THREADS) void k_stereo(StereoArgs a) {
+  constexpr int G = NS < 64 ? NS : 64;
+  constexpr int GPW = 64 / G;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int grp = lane / G;
+  const int count = a.scal_ro->mask_count;
+  const int groups_per_block = ST_WAVES * GPW;
+  const int ngroups = gridDim.x * groups_per_block;
+  const int my_group = blockIdx.x * groups_per_block + wave * GPW + grp;
+  const int rounds = (count + ngroups - 1) / ngroups;
+  int updated_here = 0;
+  for (int r = 0; r < rounds; ++r) {      // wave-uniform trip count (cross-lane operations inside)
+    const int idx = my_group + r * ngroups;
+    const bool active = idx < count;
+    if (stereo_pixel<T, TI, PAT, NS>(a, active ? idx : 0, active, lane)) ++updated_here;
   }
   // one atomic per wavefront
   for (int m = 32; m > 0; m >>= 1) updated_here += __shfl_xor(updated_here, m, 64);
   if (lane == 0 && updated_here) atomicAdd(&a.scal->n_updated, updated_here);
+}
+
+// Prefix sums of n per-keyframe counts in LDS (pref[0] = 0, pref[n] = total).
+template <typename F>
+__device__ inline void block_prefix(int n, F count, int* pref) {
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    pref[0] = 0;
+    for (int c = 0; c < n; ++c) {
+      acc += count(c);
+      pref[c + 1] = acc;
+    }
+  }
+  __syncthreads();
+}
+
+// Keyframe c with pref[c] <= item < pref[c + 1].
+__device__ inline int find_keyframe(const int* pref, int n, int item) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (pref[mid] <= item) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Batched form: the textured pixels of n keyframes form one item space.
+template <typename T, typename TI, int PAT, int NS>
+__global__ __launch_bounds__(ST_THREADS) void k_stereo_batch(const StereoArgs* tab, int n) {
+  constexpr int G = NS < 64 ? NS : 64;
+  constexpr int GPW = 64 / G;
+  __shared__ int pref[KF_BATCH_MAX + 1];
+  __shared__ int upd[KF_BATCH_MAX];
+  for (int c = threadIdx.x; c < n; c += blockDim.x) upd[c] = 0;
+  block_prefix(n, [&](int c) { return tab[c].scal_ro->mask_count; }, pref);
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int grp = lane / G;
+  const int total = pref[n];
+  const int groups_per_block = ST_WAVES * GPW;
+  const int ngroups = gridDim.x * groups_per_block;
+  const int my_group = blockIdx.x * groups_per_block + wave * GPW + grp;
+  const int rounds = (total + ngroups - 1) / ngroups;
+  for (int r = 0; r < rounds; ++r) {
+    const int item = my_group + r * ngroups;
+    const bool active = item < total;
+    const int c = active ? find_keyframe(pref, n, item) : 0;
+    if (stereo_pixel<T, TI, PAT, NS>(tab[c], active ? item - pref[c] : 0, active, lane)) atomicAdd(&upd[c], 1);
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < n; c += blockDim.x)
+    if (upd[c]) atomicAdd(&tab[c].scal->n_updated, upd[c]);
 }
 
 // Copies the caller's frame into rows of `st` bytes, zero padded, plus one zero row.
@@ -414,6 +478,41 @@ __global__ void k_stage_frame(const uint8_t* src, uint8_t* dst, int W, int H, in
     const int r = i / st, c = i - r * st;
     dst[i] = (r < H && c < W) ? src[(size_t)r * W + c] : (uint8_t)0;
   }
+}
+
+// Batched staging: every keyframe's frame, plus a reset of its update counter.
+__global__ void k_stage_batch(const StereoArgs* tab, int n) {
+  __shared__ int pref[KF_BATCH_MAX + 1];
+  block_prefix(n, [&](int c) { return (tab[c].H + 1) * tab[c].i1_stride; }, pref);
+  const int total = pref[n];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+    const int c = find_keyframe(pref, n, i);
+    const StereoArgs& a = tab[c];
+    const int k = i - pref[c];
+    const int r = k / a.i1_stride, col = k - r * a.i1_stride;
+    a.i1s[k] = (r < a.H && col < a.W) ? a.i1[(size_t)r * a.W + col] : (uint8_t)0;
+  }
+  if (blockIdx.x == 0)
+    for (int c = threadIdx.x; c < n; c += blockDim.x) tab[c].scal->n_updated = 0;
+}
+
+template <typename T, typename TI, int PAT>
+hipError_t stereo_batch_ns(int ns, const StereoArgs* tab, int n, int blocks, hipStream_t s) {
+  switch (ns) {
+#define KF_NS(v) case v: hipLaunchKernelGGL((k_stereo_batch<T, TI, PAT, v>), dim3(blocks), dim3(ST_THREADS), 0, s, tab, n); break;
+    KF_NS(4) KF_NS(8) KF_NS(16) KF_NS(32) KF_NS(64) KF_NS(128) KF_NS(256) KF_NS(512) KF_NS(1024)
+#undef KF_NS
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int PREC>
+hipError_t stereo_batch_prec(int pattern, int ns, const StereoArgs* tab, int n, int blocks, hipStream_t s) {
+  using T = typename Form<PREC>::T;
+  using TI = typename Form<PREC>::TI;
+  if (pattern == KF_PAT_LINE5) return stereo_batch_ns<T, TI, KF_PAT_LINE5>(ns, tab, n, blocks, s);
+  return stereo_batch_ns<T, TI, KF_PAT_SQ5X5>(ns, tab, n, blocks, s);
 }
 
 template <typename T, typename TI, int PAT>
@@ -441,6 +540,17 @@ int stereo_grid_blocks(int device) {
   int cus = 256;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) cus = 256;
   return cus * 8;
+}
+
+hipError_t launch_stereo_batch(int prec, int pattern, int ns, const StereoArgs* tab, int n, int blocks,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_stage_batch, dim3(blocks), dim3(256), 0, s, tab, n);
+  switch (prec) {
+    case KF_F64: return stereo_batch_prec<KF_F64>(pattern, ns, tab, n, blocks, s);
+    case KF_F32: return stereo_batch_prec<KF_F32>(pattern, ns, tab, n, blocks, s);
+    case KF_BF16_F32: return stereo_batch_prec<KF_BF16_F32>(pattern, ns, tab, n, blocks, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_stereo(int prec, int pattern, int ns, const StereoArgs& a, int blocks, hipStream_t s) {

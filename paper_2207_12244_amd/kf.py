@@ -60,6 +60,15 @@ class KfFrameStats(ctypes.Structure):
     ]
 
 
+class KfBatchConfig(ctypes.Structure):
+    _fields_ = [
+        ("stream", c_void_p), ("use_graph", c_int32), ("workspace", c_void_p), ("workspace_bytes", c_size_t),
+    ]
+
+
+KF_BATCH_MAX_MEMBERS = 256
+
+
 class KfError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{status_string(status)}: {msg}")
@@ -96,6 +105,13 @@ def load_library(path: Optional[str] = None):
         "kf_export_state": (c_int32, [P, P, P, P, P, POINTER(c_double)]),
         "kf_solver_layout": (c_int32, [P, POINTER(c_int32)]),
         "kf_import_state": (c_int32, [P, P, P, P, POINTER(c_double)]),
+        "kf_batch_config_default": (None, [POINTER(KfBatchConfig)]),
+        "kf_batch_workspace_bytes": (c_size_t, [POINTER(P), c_int32]),
+        "kf_batch_create": (c_int32, [POINTER(P), c_int32, POINTER(KfBatchConfig), POINTER(P)]),
+        "kf_batch_fuse": (c_int32, [P, POINTER(P), POINTER(c_double)]),
+        "kf_batch_layout": (c_int32, [P, POINTER(c_int32)]),
+        "kf_batch_last_error": (c_char_p, [P]),
+        "kf_batch_destroy": (None, [P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -109,6 +125,8 @@ EXPORTED_SYMBOLS = (
     "kf_config_default", "kf_workspace_bytes", "kf_create", "kf_destroy", "kf_last_error", "kf_status_string",
     "kf_set_prior", "kf_stereo_update", "kf_solve", "kf_fuse_frame", "kf_read_depth", "kf_read_stats",
     "kf_export_state", "kf_import_state", "kf_solver_layout",
+    "kf_batch_config_default", "kf_batch_workspace_bytes", "kf_batch_create", "kf_batch_fuse", "kf_batch_layout",
+    "kf_batch_last_error", "kf_batch_destroy",
 )
 
 
@@ -198,6 +216,57 @@ def kf_solver_layout(ctx):
 def kf_import_state(ctx, x=None, rho=None, rho_var=None, tau: Optional[float] = None) -> None:
     tp = ctypes.byref(c_double(float(tau))) if tau is not None else None
     _check(load_library().kf_import_state(ctx, x, rho, rho_var, tp), ctx)
+
+
+def _bcheck(status: int, batch=None):
+    if status != KF_OK:
+        msg = load_library().kf_batch_last_error(batch).decode() if batch else ""
+        raise KfError(status, msg)
+
+
+def _ctx_array(ctxs):
+    arr = (c_void_p * len(ctxs))()
+    for i, c in enumerate(ctxs):
+        arr[i] = c.value if isinstance(c, c_void_p) else c
+    return arr
+
+
+def kf_batch_config_default() -> KfBatchConfig:
+    cfg = KfBatchConfig()
+    load_library().kf_batch_config_default(ctypes.byref(cfg))
+    return cfg
+
+
+def kf_batch_workspace_bytes(ctxs) -> int:
+    arr = _ctx_array(ctxs)
+    return int(load_library().kf_batch_workspace_bytes(arr, len(ctxs)))
+
+
+def kf_batch_create(ctxs, cfg: KfBatchConfig):
+    out = c_void_p()
+    arr = _ctx_array(ctxs)
+    _check(load_library().kf_batch_create(arr, len(ctxs), ctypes.byref(cfg), ctypes.byref(out)))
+    return out
+
+
+def kf_batch_fuse(batch, images, poses) -> None:
+    """images: sequence of device pointers (int or c_void_p); poses: sequence of 4x4 matrices."""
+    n = len(images)
+    arr = (c_void_p * n)()
+    for i, p in enumerate(images):
+        arr[i] = p.value if isinstance(p, c_void_p) else p
+    P = np.ascontiguousarray(np.stack([np.asarray(T, dtype=np.float64).reshape(4, 4) for T in poses]), np.float64)
+    _bcheck(load_library().kf_batch_fuse(batch, arr, P.ctypes.data_as(POINTER(c_double))), batch)
+
+
+def kf_batch_layout(batch):
+    out = (c_int32 * 4)()
+    _bcheck(load_library().kf_batch_layout(batch, out), batch)
+    return dict(workgroups=out[0], threads=out[1], ppt=out[2], max_queue=out[3])
+
+
+def kf_batch_destroy(batch) -> None:
+    load_library().kf_batch_destroy(batch)
 
 
 # ---------------------------------------------------------------- torch convenience layer
@@ -320,3 +389,56 @@ class Keyframe:
                         self._map(rho, "rho") if rho is not None else None,
                         self._map(var, "var") if var is not None else None,
                         tau)
+
+
+class Batch:
+    """Fuses one frame into each of several Keyframe objects with one staging,
+    one stereo and one persistent solver launch (replayed as a HIP graph).
+
+    Members must share precision, pattern, n_samples, the solver workgroup
+    size, the CG variant and the stream; each keeps its own size and tiling,
+    and its results equal those of fusing it alone.
+    """
+
+    def __init__(self, keyframes, *, use_graph: bool = True):
+        torch = _torch()
+        self.members = list(keyframes)
+        if not self.members:
+            raise ValueError("a batch needs at least one keyframe")
+        streams = {kf.stream.cuda_stream for kf in self.members}
+        if len(streams) != 1:
+            raise ValueError("batch members must share one stream")
+        self.stream = self.members[0].stream
+        ctxs = [kf.ctx for kf in self.members]
+        nbytes = kf_batch_workspace_bytes(ctxs)
+        if nbytes == 0:
+            raise KfError(KF_ERR_ARG, "invalid batch members")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        cfg = kf_batch_config_default()
+        cfg.stream = c_void_p(self.stream.cuda_stream)
+        cfg.use_graph = int(bool(use_graph))
+        cfg.workspace = c_void_p((self.workspace.data_ptr() + 255) & ~255)
+        cfg.workspace_bytes = nbytes
+        self.cfg = cfg
+        self.batch = kf_batch_create(ctxs, cfg)
+
+    def fuse(self, images, poses):
+        if len(images) != len(self.members) or len(poses) != len(self.members):
+            raise ValueError(f"need {len(self.members)} images and poses")
+        ptrs = [kf._img(im, f"images[{i}]") for i, (kf, im) in enumerate(zip(self.members, images))]
+        self._keep = list(images)
+        kf_batch_fuse(self.batch, ptrs, poses)
+
+    def layout(self):
+        return kf_batch_layout(self.batch)
+
+    def close(self):
+        if getattr(self, "batch", None) is not None:
+            kf_batch_destroy(self.batch)
+            self.batch = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -123,3 +123,51 @@ def test_binding_keyword_surface():
     src = open(_os.path.join(ROOT, "paper_2207_12244_amd", "kf.py")).read()
     ast.parse(src)
     assert "cfg.cg_variant" in src
+
+
+def _ctx(kf, W, H, **fields):
+    cfg = kf.kf_config_default(W, H)
+    for k, v in fields.items():
+        setattr(cfg, k, v)
+    cfg.workspace = ctypes.c_void_p(1 << 20)
+    cfg.workspace_bytes = kf.kf_workspace_bytes(cfg)
+    assert cfg.workspace_bytes > 0
+    return kf.kf_create(cfg)
+
+
+def test_batch_rejects_incompatible_members_on_the_host():
+    kf, lib = _lib()
+    a = _ctx(kf, 160, 120, solver_threads=512)
+    b = _ctx(kf, 320, 240, solver_threads=512)
+    c = _ctx(kf, 160, 120, solver_threads=512, pattern=kf.KF_PAT_SQ5X5)
+    d = _ctx(kf, 160, 120, solver_threads=256)
+    e = _ctx(kf, 160, 120, solver_threads=512, precision=kf.KF_F64)
+    try:
+        n = kf.kf_batch_workspace_bytes([a, b])
+        assert n > 0
+        assert kf.kf_batch_workspace_bytes([]) == 0
+        cfg = kf.kf_batch_config_default()
+        assert cfg.use_graph == 1
+        cfg.workspace = ctypes.c_void_p(1 << 24)
+        cfg.workspace_bytes = n
+        out = ctypes.c_void_p()
+        for members in ([a, c], [a, d], [a, e], [a, a]):
+            arr = kf._ctx_array(members)
+            assert lib.kf_batch_create(arr, len(members), ctypes.byref(cfg), ctypes.byref(out)) == kf.KF_ERR_ARG
+            assert not out.value
+        arr = kf._ctx_array([a, b])
+        cfg.workspace_bytes = n - 1
+        assert lib.kf_batch_create(arr, 2, ctypes.byref(cfg), ctypes.byref(out)) == kf.KF_ERR_OOM
+        cfg.workspace_bytes = n
+        cfg.workspace = ctypes.c_void_p((1 << 24) + 8)
+        assert lib.kf_batch_create(arr, 2, ctypes.byref(cfg), ctypes.byref(out)) == kf.KF_ERR_ARG
+        cfg.workspace = ctypes.c_void_p(1 << 24)
+        cfg.use_graph = 2
+        assert lib.kf_batch_create(arr, 2, ctypes.byref(cfg), ctypes.byref(out)) == kf.KF_ERR_ARG
+        assert lib.kf_batch_create(arr, 0, ctypes.byref(cfg), ctypes.byref(out)) == kf.KF_ERR_ARG
+        assert lib.kf_batch_fuse(None, None, None) == kf.KF_ERR_ARG
+        assert lib.kf_batch_last_error(None) == b"no batch"
+        lib.kf_batch_destroy(None)
+    finally:
+        for h in (a, b, c, d, e):
+            kf.kf_destroy(h)
