@@ -12,6 +12,11 @@ A step = keyframe init + 30 x (stereo update + solve) + depth read-out.
 Prints one JSON line: Mpixel/s of fused frames (30 x 640 x 480 per step),
 p50/p99 per-frame fuse latency, the solver kernel's roofline figure and the
 CPU oracle baseline.
+
+The same line carries, under "batched", the batched form: 64 keyframes of
+mixed size (160x120, 320x240, 512x384, 640x480; bf16 images, f32 maps,
+LINE5, N_s = 32, 10 x 20), each fused with one new frame per step by one
+stereo and one persistent solver launch (graph replays).
 """
 
 from __future__ import annotations
@@ -31,10 +36,13 @@ sys.path.insert(0, ROOT)
 METRIC = "fused keyframe-update Mpixel/s at 640x480 + p50/p99 fuse latency"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "solver_640x480_traffic.json")
+BATCH_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "solver_batched64_traffic.json")
 SOLVER_SRC = os.path.join(ROOT, "paper_2207_12244_amd", "csrc", "kf_solve.hip")
 
 WORKLOAD = dict(config=2, W=640, H=480, frames=30, precision="bf16", pattern="sq5x5", n_samples=128,
                 n_gn=10, n_cg=20)
+BATCHED = dict(config=3, keyframes=64, precision="bf16", pattern="line5", n_samples=32, n_gn=10, n_cg=20,
+               solver_threads=512)
 
 
 def solver_bytes_per_frame(N, n_gn, n_cg, word=4):
@@ -49,11 +57,11 @@ def source_hash(path):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def load_traffic():
-    """HBM bytes per solver launch from the committed rocprofv3 counter summary,
+def load_traffic(path=TRAFFIC_FILE):
+    """HBM bytes per solver launch from a committed rocprofv3 counter summary,
     or None when the solver source changed since the counters were taken."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -79,32 +87,122 @@ def cpu_baseline(case, wl):
                       f"{wall:.1f} s wall on the host", "seconds": round(wall, 3)}
 
 
-def main(argv=None):
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--tiles", default="0x0", help="solver tile grid TXxTY (0x0 = automatic)")
-    ap.add_argument("--solver-threads", type=int, default=0, help="solver workgroup size (0 = automatic)")
-    ap.add_argument("--cooperative", action="store_true", help="launch the solver cooperatively")
-    ap.add_argument("--cg-variant", default="auto", choices=["auto", "textbook", "pipelined"])
-    ap.add_argument("--calibrate-copy", action="store_true",
-                    help="first run a plain 256 MiB device-to-device copy (HBM counter calibration)")
-    a = ap.parse_args(argv)
-    if a.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {a.gpus}); "
-              "independent keyframes shard across GPUs without communication, see the design notes.",
-              file=sys.stderr)
-        return 2
+def _gen_batched_case(i):
+    import kfsynth
+    return kfsynth.config_case(BATCHED["config"], i)
 
-    import torch
+
+def batched_cases(n):
+    """The batched workload's keyframes (seeded size per keyframe), generated in a process pool."""
+    import concurrent.futures
+    import multiprocessing
+    t_gen = time.perf_counter()
+    workers = max(1, min(8, os.cpu_count() or 1))
+    ctx = multiprocessing.get_context("fork")
+    with concurrent.futures.ProcessPoolExecutor(workers, mp_context=ctx) as ex:
+        cases = list(ex.map(_gen_batched_case, range(n)))
+    print(f"# batched: generated {len(cases)} keyframes in {time.perf_counter() - t_gen:.1f}s",
+          file=sys.stderr, flush=True)
+    return cases
+
+
+def cpu_baseline_batched(case, wl):
+    """The FP64 oracle, as it stands, fusing one keyframe of the batch (the first
+    160 x 120 one) with its frame, timed on the host."""
+    from oracle import OracleKeyframe, SolverParams, StereoParams
+    ok = OracleKeyframe(case.K, case.W, case.H, StereoParams(n_samples=wl["n_samples"], pattern=wl["pattern"]),
+                        SolverParams(n_gn=wl["n_gn"], n_cg=wl["n_cg"], linear_solver="pcg"))
+    ok.set_prior(case.image0, *case.priors.maps(), case.T_wc0)
+    w0, c0 = time.perf_counter(), time.process_time()
+    ok.fuse_frame(case.images[0], case.poses[0])
+    w1, c1 = time.perf_counter(), time.process_time()
+    wall = w1 - w0
+    cores = max(1, int(round((c1 - c0) / wall)))
+    return {"value": round(case.W * case.H / wall / 1e6, 6), "unit": "Mpixel/s", "cores": cores, "kind": "oracle",
+            "sample": f"1 keyframe of the batch ({case.W}x{case.H}) fused with its frame, {wall:.1f} s wall",
+            "seconds": round(wall, 3)}
+
+
+def run_batched(a, torch, cases):
+    """Batched form: one step = one new frame fused into each of 64 keyframes."""
+    from paper_2207_12244_amd.kf import Batch, Keyframe
+    wl = BATCHED
+    dev = lambda x, dt: torch.as_tensor(np.ascontiguousarray(x), dtype=dt, device="cuda")
+    members, imgs, poses = [], [], []
+    for c in cases:
+        kf = Keyframe(c.W, c.H, K=c.K, precision=wl["precision"], pattern=wl["pattern"], n_samples=wl["n_samples"],
+                      n_gn=wl["n_gn"], n_cg=wl["n_cg"], solver_threads=wl["solver_threads"])
+        kf.set_prior(dev(c.image0, torch.uint8), *[dev(m, torch.float32) for m in c.priors.maps()], c.T_wc0)
+        members.append(kf)
+        imgs.append(dev(c.images[0], torch.uint8))
+        poses.append(c.poses[0])
+    batch = Batch(members)
+    stream = members[0].stream
+    steps = a.batched_steps
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+
+    def step(k):
+        if k is not None:
+            ev[k][0].record(stream)
+        batch.stereo_update(imgs, poses)
+        if k is not None:
+            ev[k][1].record(stream)
+        batch.solve()
+        if k is not None:
+            ev[k][2].record(stream)
+
+    for _ in range(a.warmup):
+        step(None)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        step(k)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    stereo_ms = [ev[k][0].elapsed_time(ev[k][1]) for k in range(steps)]
+    solve_ms = [ev[k][1].elapsed_time(ev[k][2]) for k in range(steps)]
+    lat_ms = [ev[k][0].elapsed_time(ev[k][2]) for k in range(steps)]
+    px = sum(c.W * c.H for c in cases)
+    bpl = sum(solver_bytes_per_frame(c.W * c.H, wl["n_gn"], wl["n_cg"]) for c in cases)
+    solve_avg_s = float(np.mean(solve_ms)) / 1000.0
+    achieved = bpl / solve_avg_s / 1e9
+    sizes = {}
+    for c in cases:
+        sizes[f"{c.W}x{c.H}"] = sizes.get(f"{c.W}x{c.H}", 0) + 1
+    out = {
+        "value": round(px * steps / total / 1e6, 3), "unit": "Mpixel/s", "steps": steps,
+        "ms_per_step": round(1000.0 * total / steps, 3),
+        "config": {"workload": f"{len(cases)} keyframes of mixed size, each fused with one new frame per step; "
+                               f"bf16 images, f32 maps and arithmetic, LINE5, N_s={wl['n_samples']}, "
+                               f"{wl['n_gn']} GN x {wl['n_cg']} PCG",
+                   "sizes": sizes, "pixels_per_step": px,
+                   "seeds": f"{kfsynth_seed(wl['config'], 0)}..{kfsynth_seed(wl['config'], len(cases) - 1)}",
+                   "solver_launch": batch.layout()},
+        "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 4),
+                       "p99": round(float(np.percentile(lat_ms, 99)), 4)},
+        "stage_ms_per_step": {"stereo": round(float(np.mean(stereo_ms)), 4),
+                              "solve": round(float(np.mean(solve_ms)), 4)},
+        "roofline": {"kernel": "k_solve_batch", "bound": "hbm", "achieved": round(achieved, 2),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": load_traffic(BATCH_TRAFFIC_FILE), "algorithmic_bytes_per_launch": bpl,
+                     "avg_launch_ms": round(solve_avg_s * 1000.0, 4)},
+    }
+    if not a.no_cpu_baseline:
+        small = next((c for c in cases if c.W == 160), cases[0])
+        out["cpu_baseline"] = cpu_baseline_batched(small, wl)
+    batch.close()
+    return out
+
+
+def kfsynth_seed(config, case):
+    import kfsynth
+    return kfsynth.seed_for(config, case)
+
+
+def run_headline(a, torch):
+    """The headline workload: one 640 x 480 keyframe fused with a 30-frame sequence."""
     import kfsynth
     from paper_2207_12244_amd.kf import Keyframe
-
-    if not torch.cuda.is_available():
-        print("bench.py needs a GPU", file=sys.stderr)
-        return 2
     wl = WORKLOAD
     if a.calibrate_copy:
         # known traffic: reads 256 MiB and writes 256 MiB
@@ -203,6 +301,47 @@ def main(argv=None):
     }
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case, wl)
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tiles", default="0x0", help="solver tile grid TXxTY (0x0 = automatic)")
+    ap.add_argument("--solver-threads", type=int, default=0, help="solver workgroup size (0 = automatic)")
+    ap.add_argument("--cooperative", action="store_true", help="launch the solver cooperatively")
+    ap.add_argument("--cg-variant", default="auto", choices=["auto", "textbook", "pipelined"])
+    ap.add_argument("--form", default="all", choices=["all", "headline", "batched"],
+                    help="headline 640x480 sequence, the batched form, or both (batched under \"batched\")")
+    ap.add_argument("--batched-steps", type=int, default=10)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain 256 MiB device-to-device copy (HBM counter calibration)")
+    a = ap.parse_args(argv)
+    if a.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {a.gpus}); "
+              "independent keyframes shard across GPUs without communication, see the design notes.",
+              file=sys.stderr)
+        return 2
+
+    # the batched workload is generated in a process pool before the GPU is touched
+    batched_in = batched_cases(BATCHED["keyframes"]) if a.form in ("all", "batched") else None
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    if a.form == "batched":
+        out = run_batched(a, torch, batched_in)
+        out = {"metric": "batched keyframe-update Mpixel/s (64 mixed-size keyframes)", **out, "n_gpus": 1,
+               "warmup": a.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+               "data": "synthetic"}
+    else:
+        out = run_headline(a, torch)
+        if batched_in is not None:
+            out["batched"] = run_batched(a, torch, batched_in)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -93,7 +93,7 @@ typedef struct {
   int32_t precision;            /* kf_precision */
   int32_t solver_tiles_x;       /* solver workgroup grid (0, 0 = automatic) */
   int32_t solver_tiles_y;
-  int32_t solver_threads;       /* threads per solver workgroup: 0 = automatic, 256 or 512 */
+  int32_t solver_threads;       /* threads per solver workgroup: 0 = automatic, 256, 512 or 1024 */
   int32_t solver_cooperative;   /* 1: hipLaunchCooperativeKernel; 0: plain launch whose grid is
                                    checked against the device's co-resident capacity */
   void* stream;                 /* hipStream_t the context enqueues on (NULL = null stream) */
@@ -218,6 +218,14 @@ kf_status kf_batch_create(kf_ctx* const* members, int32_t n, const kf_batch_conf
    report device errors. Blocks the host only while the descriptor buffer it
    reuses (that of the call before last) is still being uploaded. */
 kf_status kf_batch_fuse(kf_batch* batch, const uint8_t* const* images, const double* poses);
+
+/* The two halves of kf_batch_fuse, for callers that time or interleave them:
+   the stereo update of every member (staging + stereo launches), and the
+   optimisation of every member (the persistent solver launch). Same
+   arguments, conditions and results as the corresponding parts of
+   kf_batch_fuse. */
+kf_status kf_batch_stereo_update(kf_batch* batch, const uint8_t* const* images, const double* poses);
+kf_status kf_batch_solve(kf_batch* batch);
 
 /* Solver launch of the batch: workgroups, threads per workgroup, pixels per
    thread, and the longest per-workgroup team queue. */

@@ -41,8 +41,8 @@ const char* validate(const kf_config& c) {
   if (c.precision != KF_F64 && c.precision != KF_F32 && c.precision != KF_BF16_F32) return "unknown precision";
   if ((c.solver_tiles_x == 0) != (c.solver_tiles_y == 0) || c.solver_tiles_x < 0 || c.solver_tiles_y < 0)
     return "solver_tiles_x/y must both be 0 (automatic) or both positive";
-  if (c.solver_threads != 0 && c.solver_threads != 256 && c.solver_threads != 512)
-    return "solver_threads must be 0, 256 or 512";
+  if (c.solver_threads != 0 && c.solver_threads != 256 && c.solver_threads != 512 && c.solver_threads != 1024)
+    return "solver_threads must be 0, 256, 512 or 1024";
   if (c.solver_cooperative != 0 && c.solver_cooperative != 1) return "solver_cooperative must be 0 or 1";
   if (c.cg_variant < 0 || c.cg_variant > 2) return "cg_variant must be 0, 1 or 2";
   if (c.cg_variant == 2 && c.cg_rtol > 0.0) return "the pipelined CG variant runs a fixed iteration count (cg_rtol = 0)";
@@ -52,13 +52,13 @@ const char* validate(const kf_config& c) {
 // Largest pixels-per-thread whose solver instantiation keeps every value in
 // registers (VGPRs, or AGPRs as spill space for 256-thread workgroups).
 int ppt_max(int prec, int threads) {
-  if (prec == KF_F64) return threads == 256 ? 4 : 2;
-  return threads == 256 ? 6 : 3;
+  if (prec == KF_F64) return threads == 256 ? 6 : (threads == 512 ? 4 : 1);
+  return threads == 256 ? 8 : (threads == 512 ? 10 : 3);
 }
 
 int ppt_for(int px, int threads, int prec) {
   const int need = (px + threads - 1) / threads;
-  static const int opts[] = {1, 2, 3, 4, 6};
+  static const int opts[] = {1, 2, 3, 4, 6, 8, 10};
   for (int o : opts)
     if (o >= need) return o <= ppt_max(prec, threads) ? o : 0;
   return 0;
@@ -83,14 +83,19 @@ bool tiling_ok(int W, int H, int tx, int ty, int threads, int prec, Tiling* t) {
 
 }  // namespace
 
-// Picks the tile grid minimising a latency model of one PCG iteration:
-// team synchronisation ~1.1 us + 6.5 ns per workgroup (measured on MI355X)
-// plus the per-workgroup stencil work (~30 VALU ops per pixel at 64 lanes per
-// clock, 2.4 GHz; x2 for 256-thread workgroups, whose single wavefront per
-// SIMD hides no latency, x1.4 for 512 threads), with a small penalty for long
-// tile perimeters.
+// Latency model of one PCG iteration of a team (microseconds), fitted to
+// MI355X measurements of the 640 x 480 solve: a synchronisation costs ~2.1 us
+// plus 6.5 ns per workgroup polled, and a workgroup spends ~0.85 ns per tile
+// pixel at 512 threads (0.95 at 1024, 1.65 at 256, whose single wavefront per
+// SIMD hides little latency), with a small penalty for long tile perimeters.
+double iteration_us(const Tiling& c) {
+  const double per_px = c.threads == 256 ? 1.65e-3 : (c.threads == 512 ? 0.85e-3 : 0.95e-3);
+  return 2.1 + 0.0065 * c.blocks + (double)c.tile_w * c.tile_h * per_px + (c.tile_w + c.tile_h) * 1e-4;
+}
+
+// Picks the tile grid (and workgroup size, unless given) minimising iteration_us.
 bool choose_tiling(int W, int H, int tx_req, int ty_req, int threads_req, int prec, Tiling* t) {
-  const int thr_opts[2] = {512, 256};
+  const int thr_opts[3] = {512, 256, 1024};
   if (tx_req > 0 && ty_req > 0) {
     for (int nt : thr_opts) {
       if (threads_req && nt != threads_req) continue;
@@ -108,10 +113,7 @@ bool choose_tiling(int W, int H, int tx_req, int ty_req, int threads_req, int pr
         if (tx * ty > MAX_TEAM) break;
         Tiling c;
         if (!tiling_ok(W, H, tx, ty, nt, prec, &c)) continue;
-        const double sync_us = 1.1 + 0.0065 * c.blocks;
-        const double work_us = (double)c.tile_w * c.tile_h * 30.0 / 64.0 / 2400.0 * (nt == 256 ? 2.0 : 1.4);
-        const double perim_us = (c.tile_w + c.tile_h) * 1e-4;
-        const double cost = sync_us + work_us + perim_us;
+        const double cost = iteration_us(c);
         if (cost < best) {
           best = cost;
           bt = c;

@@ -35,14 +35,14 @@ struct kf_batch {
   hipEvent_t ev[2] = {nullptr, nullptr};
   bool ev_used[2] = {false, false};
   int parity = 0;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  // captured launch sequences: 0 = stereo + solve, 1 = stereo, 2 = solve
+  hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};
   std::vector<int32_t> queue, qoff;
   std::string err;
 
   ~kf_batch() {
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
+    for (hipGraphExec_t g : exec)
+      if (g) (void)hipGraphExecDestroy(g);
     for (int i = 0; i < 2; ++i) {
       if (ev[i]) {
         (void)hipEventSynchronize(ev[i]);
@@ -88,16 +88,12 @@ WsLayout ws_layout(int n, int members) {
   return L;
 }
 
-// Estimated duration of one keyframe's solve (arbitrary units): per
-// synchronisation the team's polling cost plus its tile's stencil work, the
-// same latency model as the single-keyframe tiling choice.
+// Estimated duration of one keyframe's solve (microseconds): the latency
+// model of the single-keyframe tiling choice times the synchronisations.
 double team_cost(const kf_ctx* c) {
   const kf_config& g = c->cfg;
-  const Tiling& t = c->tiling;
-  const double per_sync = 1.1 + 0.0065 * t.blocks + (double)t.tile_w * t.tile_h * 30.0 / 64.0 / 2400.0 *
-                                                        (t.threads == 256 ? 2.0 : 1.4);
   const double cg = g.cg_rtol > 0.0 ? (double)g.cg_max : (double)g.n_cg;
-  return g.n_gn * (cg + 2.0) * per_sync;
+  return g.n_gn * (cg + 2.0) * iteration_us(c->tiling);
 }
 
 // List schedule of the teams over `grid` workgroups: teams in order of
@@ -141,22 +137,99 @@ void schedule(kf_batch* b) {
   }
 }
 
-hipError_t enqueue_frame(kf_batch* b, hipStream_t s) {
-  const int n = (int)b->m.size();
-  hipError_t e = launch_stereo_batch(b->prec, b->pattern, b->ns, b->d_st, n, b->stereo_blocks, s);
-  if (e != hipSuccess) return e;
+hipError_t enqueue_stereo(kf_batch* b, hipStream_t s) {
+  return launch_stereo_batch(b->prec, b->pattern, b->ns, b->d_st, (int)b->m.size(), b->stereo_blocks, s);
+}
+
+hipError_t enqueue_solve(kf_batch* b, hipStream_t s) {
   return launch_solve_batch(b->prec, b->threads, b->ppt, b->pipelined, b->d_so, b->d_queue, b->d_qoff, b->grid,
                             b->smem, s);
 }
 
-hipError_t build_graph(kf_batch* b) {
+hipError_t enqueue(kf_batch* b, int which, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  if (which != 2) e = enqueue_stereo(b, s);
+  if (e == hipSuccess && which != 1) e = enqueue_solve(b, s);
+  return e;
+}
+
+// Captures launch sequence `which` once on the private stream.
+hipError_t graph_for(kf_batch* b, int which) {
+  if (b->exec[which]) return hipSuccess;
   hipError_t e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return e;
-  hipError_t el = enqueue_frame(b, b->capture);
-  e = hipStreamEndCapture(b->capture, &b->graph);
-  if (el != hipSuccess) return el;
+  const hipError_t el = enqueue(b, which, b->capture);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(b->capture, &g);
+  if (el != hipSuccess || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return el != hipSuccess ? el : e;
+  }
+  e = hipGraphInstantiate(&b->exec[which], g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  return e;
+}
+
+hipError_t run(kf_batch* b, int which) {
+  if (!b->use_graph) return enqueue(b, which, b->stream);
+  hipError_t e = graph_for(b, which);
   if (e != hipSuccess) return e;
-  return hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+  return hipGraphLaunch(b->exec[which], b->stream);
+}
+
+// Validates the frame, writes the per-frame descriptors into the free pinned
+// buffer and enqueues their upload.
+kf_status upload_frame(kf_batch* b, const uint8_t* const* images, const double* poses, const char* who) {
+  const int n = (int)b->m.size();
+  if (!images || !poses) return bfail(b, KF_ERR_ARG, std::string(who) + ": NULL images or poses");
+  for (int i = 0; i < n; ++i) {
+    if (!b->m[i]->has_prior)
+      return bfail(b, KF_ERR_STATE, std::string(who) + ": member " + std::to_string(i) + " has no prior (kf_set_prior)");
+    if (!images[i]) return bfail(b, KF_ERR_ARG, std::string(who) + ": NULL image for member " + std::to_string(i));
+    if (!pose_ok(poses + 16 * (size_t)i))
+      return bfail(b, KF_ERR_ARG, std::string(who) + ": pose of member " + std::to_string(i) +
+                                  " must be finite with last row 0 0 0 1");
+  }
+  // the pinned buffer of this parity was last read by the upload two calls ago
+  const int p = b->parity;
+  hipError_t e = hipSuccess;
+  if (b->ev_used[p]) {
+    e = hipEventSynchronize(b->ev[p]);
+    if (e != hipSuccess) return bhip(b, e, who);
+  }
+  StereoArgs* h = b->h_pin[p];
+  for (int i = 0; i < n; ++i)
+    if (!stereo_args(b->m[i], images[i], poses + 16 * (size_t)i, &h[i]))
+      return bfail(b, KF_ERR_ARG, std::string(who) + ": singular pose for member " + std::to_string(i));
+  e = hipMemcpyAsync(b->d_st, h, n * sizeof(StereoArgs), hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) e = hipEventRecord(b->ev[p], b->stream);
+  if (e != hipSuccess) return bhip(b, e, who);
+  b->ev_used[p] = true;
+  b->parity ^= 1;
+  return KF_OK;
+}
+
+kf_status check_members(kf_batch* b, const char* who) {
+  for (size_t i = 0; i < b->m.size(); ++i)
+    if (!b->m[i]->has_prior)
+      return bfail(b, KF_ERR_STATE, std::string(who) + ": member " + std::to_string(i) + " has no prior (kf_set_prior)");
+  return KF_OK;
+}
+
+kf_status pre_solve(kf_batch* b, const char* who) {
+  for (kf_ctx* c : b->m) {
+    const hipError_t e = epoch_wrap_if_needed(c, solve_epoch_bound(c->cfg));
+    if (e != hipSuccess) return bhip(b, e, who);
+  }
+  return KF_OK;
+}
+
+void post_solve(kf_batch* b) {
+  for (kf_ctx* c : b->m) c->epoch += solve_epoch_bound(c->cfg);
+}
+
+void post_stereo(kf_batch* b) {
+  for (kf_ctx* c : b->m) ++c->frame;
 }
 
 }  // namespace
@@ -256,7 +329,7 @@ kf_status kf_batch_create(kf_ctx* const* members, int32_t n, const kf_batch_conf
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev[i], hipEventDisableTiming);
   }
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
-  if (e == hipSuccess && b->use_graph) e = build_graph(b);
+  if (e == hipSuccess && b->use_graph) e = graph_for(b, 0);
   if (e != hipSuccess) {
     delete b;
     return KF_ERR_HIP;
@@ -283,42 +356,34 @@ kf_status kf_batch_layout(const kf_batch* b, int32_t out[4]) {
 
 kf_status kf_batch_fuse(kf_batch* b, const uint8_t* const* images, const double* poses) {
   if (!b) return KF_ERR_ARG;
-  if (!images || !poses) return bfail(b, KF_ERR_ARG, "kf_batch_fuse: NULL images or poses");
-  const int n = (int)b->m.size();
-  for (int i = 0; i < n; ++i) {
-    if (!b->m[i]->has_prior) return bfail(b, KF_ERR_STATE, "kf_batch_fuse: member " + std::to_string(i) +
-                                                            " has no prior (kf_set_prior)");
-    if (!images[i]) return bfail(b, KF_ERR_ARG, "kf_batch_fuse: NULL image for member " + std::to_string(i));
-    if (!pose_ok(poses + 16 * (size_t)i))
-      return bfail(b, KF_ERR_ARG, "kf_batch_fuse: pose of member " + std::to_string(i) +
-                                  " must be finite with last row 0 0 0 1");
-  }
-  // the pinned buffer of this parity was last read by the copy two calls ago
-  const int p = b->parity;
-  hipError_t e = hipSuccess;
-  if (b->ev_used[p]) {
-    e = hipEventSynchronize(b->ev[p]);
-    if (e != hipSuccess) return bhip(b, e, "kf_batch_fuse (descriptor buffer)");
-  }
-  StereoArgs* h = b->h_pin[p];
-  for (int i = 0; i < n; ++i)
-    if (!stereo_args(b->m[i], images[i], poses + 16 * (size_t)i, &h[i]))
-      return bfail(b, KF_ERR_ARG, "kf_batch_fuse: singular pose for member " + std::to_string(i));
-  for (kf_ctx* c : b->m) {
-    e = epoch_wrap_if_needed(c, solve_epoch_bound(c->cfg));
-    if (e != hipSuccess) return bhip(b, e, "kf_batch_fuse (epoch wrap)");
-  }
-  e = hipMemcpyAsync(b->d_st, h, n * sizeof(StereoArgs), hipMemcpyHostToDevice, b->stream);
-  if (e == hipSuccess) e = hipEventRecord(b->ev[p], b->stream);
-  if (e != hipSuccess) return bhip(b, e, "kf_batch_fuse (descriptor upload)");
-  b->ev_used[p] = true;
-  b->parity ^= 1;
-  e = b->use_graph ? hipGraphLaunch(b->exec, b->stream) : enqueue_frame(b, b->stream);
+  kf_status s = upload_frame(b, images, poses, "kf_batch_fuse");
+  if (s == KF_OK) s = pre_solve(b, "kf_batch_fuse");
+  if (s != KF_OK) return s;
+  const hipError_t e = run(b, 0);
   if (e != hipSuccess) return bhip(b, e, "kf_batch_fuse");
-  for (kf_ctx* c : b->m) {
-    ++c->frame;
-    c->epoch += solve_epoch_bound(c->cfg);
-  }
+  post_stereo(b);
+  post_solve(b);
+  return KF_OK;
+}
+
+kf_status kf_batch_stereo_update(kf_batch* b, const uint8_t* const* images, const double* poses) {
+  if (!b) return KF_ERR_ARG;
+  const kf_status s = upload_frame(b, images, poses, "kf_batch_stereo_update");
+  if (s != KF_OK) return s;
+  const hipError_t e = run(b, 1);
+  if (e != hipSuccess) return bhip(b, e, "kf_batch_stereo_update");
+  post_stereo(b);
+  return KF_OK;
+}
+
+kf_status kf_batch_solve(kf_batch* b) {
+  if (!b) return KF_ERR_ARG;
+  kf_status s = check_members(b, "kf_batch_solve");
+  if (s == KF_OK) s = pre_solve(b, "kf_batch_solve");
+  if (s != KF_OK) return s;
+  const hipError_t e = run(b, 2);
+  if (e != hipSuccess) return bhip(b, e, "kf_batch_solve");
+  post_solve(b);
   return KF_OK;
 }
 

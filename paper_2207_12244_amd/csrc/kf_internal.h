@@ -95,6 +95,7 @@ constexpr int CHUNK = 256;           // pixels per compaction chunk
 #define KF_BATCH_MAX KF_BATCH_MAX_MEMBERS
 
 bool choose_tiling(int W, int H, int tx_req, int ty_req, int threads_req, int prec, Tiling* t);
+double iteration_us(const Tiling& t);   // latency model of one PCG iteration
 // Workgroups of this tiling the device can hold at once (0 if unknown).
 int solve_max_coresident(int prec, const Tiling& t, bool pipelined, int device);
 bool layout_for(const kf_config& cfg, const Tiling& t, Layout* lay);

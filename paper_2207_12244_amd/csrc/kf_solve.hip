@@ -32,6 +32,12 @@ __device__ inline void st_word(uint64_t* p, uint64_t v) {
 __device__ inline uint64_t ld_word(const uint64_t* p) {
   return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// Compiler-only barrier (no instruction): the value counts as redefined here,
+// so per-pixel addresses derived from it are recomputed inside the loop that
+// holds the barrier instead of being hoisted and kept live in registers for the
+// whole launch (that cut the register count per pixel from ~53 to ~16).
+__device__ inline void refresh(int& v) { asm volatile("" : "+v"(v)); }
+
 __device__ inline uint64_t tagged(uint32_t bits, uint32_t e) { return ((uint64_t)e << 32) | (uint64_t)bits; }
 
 template <typename V> struct Wire;
@@ -147,6 +153,12 @@ struct Team {
   // loaded together each polling round. Returns false if the team aborts.
   __device__ bool sync(uint32_t e, int nv, const double* vals, double* tot, T* gval, bool ghosts, T* ring = nullptr) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+    for (int m = 0; m < GMAX; ++m) {
+      refresh(g_src[m]);
+      refresh(g_off[m]);
+      refresh(g_li[m]);
+    }
     for (int v = 0; v < nv; ++v) {
       const double s = wave_sum(vals[v]);
       if (lane == 0) s_wred[wave * NV_MAX + v] = s;
@@ -382,6 +394,8 @@ __device__ __forceinline__ void solve_member(const SolveArgs& a, const int b, un
   };
 
   for (int gn = 0; gn < a.n_gn; ++gn) {
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) refresh(lxy[j]);
     // ---- IRLS weights and 5-point normal equations at (x, tau) (Sec. II-C);
     //      r = b - A x, z = r / diag, p = z
     double rz = 0.0, r2 = 0.0, b2 = 0.0;
@@ -469,6 +483,8 @@ __device__ __forceinline__ void solve_member(const SolveArgs& a, const int b, un
       for (int i = 0; i < limit && !converged; ++i) {
         T* mring = (i & 1) ? ps : ms0;
         T* mnext = (i & 1) ? ms0 : ps;
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) refresh(lxy[j]);
         double ga = 0.0, de = 0.0;
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
@@ -515,6 +531,8 @@ __device__ __forceinline__ void solve_member(const SolveArgs& a, const int b, un
     }
     while (!PIPE && !converged && it < limit && rz_t != 0.0) {
       // q = A p (5-point stencil; ghost ring holds the neighbours' p)
+#pragma unroll
+      for (int j = 0; j < PPT; ++j) refresh(lxy[j]);
       double pq = 0.0;
 #pragma unroll
       for (int j = 0; j < PPT; ++j) {
@@ -571,6 +589,8 @@ __device__ __forceinline__ void solve_member(const SolveArgs& a, const int b, un
     cg_total += it;
 
     // ---- scale step: semi weights at (x_new, tau), tau = sum w (x - z) / sum w (R13)
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) refresh(lxy[j]);
     double num = 0.0, den = 0.0, cnt = 0.0;
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
@@ -639,6 +659,17 @@ __global__ __launch_bounds__(NT) void k_solve_batch(const SolveArgs* __restrict_
 
 namespace {
 
+// (threads, pixels per thread) combinations whose registers fit without
+// scratch spills (the ppt_max table of the host side follows these)
+#define KF_SOLVE_COMBOS                                                              \
+  KF_PPT(256, 1) KF_PPT(256, 2) KF_PPT(256, 3) KF_PPT(256, 4) KF_PPT(256, 6)          \
+  KF_PPT(512, 1) KF_PPT(512, 2) KF_PPT(512, 3) KF_PPT(512, 4)                         \
+  KF_PPT(1024, 1)                                                                     \
+  if constexpr (sizeof(T) == 4) {                                                     \
+    KF_PPT(256, 8) KF_PPT(512, 6) KF_PPT(512, 8) KF_PPT(512, 10) KF_PPT(1024, 2)      \
+    KF_PPT(1024, 3)                                                                   \
+  }
+
 size_t smem_for(size_t elt, const Tiling& t) {
   const size_t ring = (size_t)(t.tile_h + 2) * (t.tile_w + 2);
   return sizeof(double) * ((size_t)(t.threads / 64) * NV_MAX + NV_MAX * (size_t)t.blocks + 2) + 3 * ring * elt;
@@ -647,12 +678,7 @@ size_t smem_for(size_t elt, const Tiling& t) {
 template <typename T, bool PIPE>
 const void* solve_fn_p(const Tiling& t) {
 #define KF_PPT(nt, n) if (t.threads == nt && t.ppt == n) return reinterpret_cast<const void*>(&k_solve<T, nt, n, PIPE>);
-  // combinations whose registers fit without scratch spills (see ppt_max)
-  KF_PPT(256, 1) KF_PPT(256, 2) KF_PPT(256, 3) KF_PPT(256, 4)
-  KF_PPT(512, 1) KF_PPT(512, 2)
-  if (sizeof(T) == 4) {
-    KF_PPT(256, 6) KF_PPT(512, 3)
-  }
+  KF_SOLVE_COMBOS
 #undef KF_PPT
   return nullptr;
 }
@@ -665,11 +691,7 @@ const void* solve_fn(const Tiling& t, bool pipelined) {
 template <typename T, bool PIPE>
 const void* batch_fn_p(int threads, int ppt) {
 #define KF_PPT(nt, n) if (threads == nt && ppt == n) return reinterpret_cast<const void*>(&k_solve_batch<T, nt, n, PIPE>);
-  KF_PPT(256, 1) KF_PPT(256, 2) KF_PPT(256, 3) KF_PPT(256, 4)
-  KF_PPT(512, 1) KF_PPT(512, 2)
-  if (sizeof(T) == 4) {
-    KF_PPT(256, 6) KF_PPT(512, 3)
-  }
+  KF_SOLVE_COMBOS
 #undef KF_PPT
   return nullptr;
 }

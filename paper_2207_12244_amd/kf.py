@@ -109,6 +109,8 @@ def load_library(path: Optional[str] = None):
         "kf_batch_workspace_bytes": (c_size_t, [POINTER(P), c_int32]),
         "kf_batch_create": (c_int32, [POINTER(P), c_int32, POINTER(KfBatchConfig), POINTER(P)]),
         "kf_batch_fuse": (c_int32, [P, POINTER(P), POINTER(c_double)]),
+        "kf_batch_stereo_update": (c_int32, [P, POINTER(P), POINTER(c_double)]),
+        "kf_batch_solve": (c_int32, [P]),
         "kf_batch_layout": (c_int32, [P, POINTER(c_int32)]),
         "kf_batch_last_error": (c_char_p, [P]),
         "kf_batch_destroy": (None, [P]),
@@ -125,7 +127,8 @@ EXPORTED_SYMBOLS = (
     "kf_config_default", "kf_workspace_bytes", "kf_create", "kf_destroy", "kf_last_error", "kf_status_string",
     "kf_set_prior", "kf_stereo_update", "kf_solve", "kf_fuse_frame", "kf_read_depth", "kf_read_stats",
     "kf_export_state", "kf_import_state", "kf_solver_layout",
-    "kf_batch_config_default", "kf_batch_workspace_bytes", "kf_batch_create", "kf_batch_fuse", "kf_batch_layout",
+    "kf_batch_config_default", "kf_batch_workspace_bytes", "kf_batch_create", "kf_batch_fuse",
+    "kf_batch_stereo_update", "kf_batch_solve", "kf_batch_layout",
     "kf_batch_last_error", "kf_batch_destroy",
 )
 
@@ -249,14 +252,28 @@ def kf_batch_create(ctxs, cfg: KfBatchConfig):
     return out
 
 
-def kf_batch_fuse(batch, images, poses) -> None:
-    """images: sequence of device pointers (int or c_void_p); poses: sequence of 4x4 matrices."""
+def _frame_args(images, poses):
     n = len(images)
     arr = (c_void_p * n)()
     for i, p in enumerate(images):
         arr[i] = p.value if isinstance(p, c_void_p) else p
     P = np.ascontiguousarray(np.stack([np.asarray(T, dtype=np.float64).reshape(4, 4) for T in poses]), np.float64)
+    return arr, P
+
+
+def kf_batch_fuse(batch, images, poses) -> None:
+    """images: sequence of device pointers (int or c_void_p); poses: sequence of 4x4 matrices."""
+    arr, P = _frame_args(images, poses)
     _bcheck(load_library().kf_batch_fuse(batch, arr, P.ctypes.data_as(POINTER(c_double))), batch)
+
+
+def kf_batch_stereo_update(batch, images, poses) -> None:
+    arr, P = _frame_args(images, poses)
+    _bcheck(load_library().kf_batch_stereo_update(batch, arr, P.ctypes.data_as(POINTER(c_double))), batch)
+
+
+def kf_batch_solve(batch) -> None:
+    _bcheck(load_library().kf_batch_solve(batch), batch)
 
 
 def kf_batch_layout(batch):
@@ -423,11 +440,19 @@ class Batch:
         self.batch = kf_batch_create(ctxs, cfg)
 
     def fuse(self, images, poses):
+        kf_batch_fuse(self.batch, self._ptrs(images, poses), poses)
+
+    def _ptrs(self, images, poses):
         if len(images) != len(self.members) or len(poses) != len(self.members):
             raise ValueError(f"need {len(self.members)} images and poses")
-        ptrs = [kf._img(im, f"images[{i}]") for i, (kf, im) in enumerate(zip(self.members, images))]
         self._keep = list(images)
-        kf_batch_fuse(self.batch, ptrs, poses)
+        return [kf._img(im, f"images[{i}]") for i, (kf, im) in enumerate(zip(self.members, images))]
+
+    def stereo_update(self, images, poses):
+        kf_batch_stereo_update(self.batch, self._ptrs(images, poses), poses)
+
+    def solve(self):
+        kf_batch_solve(self.batch)
 
     def layout(self):
         return kf_batch_layout(self.batch)

@@ -35,23 +35,28 @@ def _assert_same(a, b, label):
     assert a["tau"] == b["tau"], label
 
 
-def _run_pair(cases, settings, frames, use_graph):
+def _run_pair(cases, settings, frames, mode):
     from paper_2207_12244_amd.kf import Batch
     t = torch()
     solo = [_make(c, **s) for c, s in zip(cases, settings)]
     members = [_make(c, **s) for c, s in zip(cases, settings)]
-    batch = Batch(members, use_graph=use_graph)
+    batch = Batch(members, use_graph=mode != "direct")
     imgs = [[dev(c.images[f], t.uint8) for c in cases] for f in range(frames)]
     for f in range(frames):
         for i, (k, c) in enumerate(zip(solo, cases)):
             k.fuse_frame(imgs[f][i], c.poses[f])
-        batch.fuse(imgs[f], [c.poses[f] for c in cases])
+        poses = [c.poses[f] for c in cases]
+        if mode == "split":
+            batch.stereo_update(imgs[f], poses)
+            batch.solve()
+        else:
+            batch.fuse(imgs[f], poses)
     t.cuda.synchronize()
     return solo, members, batch
 
 
-@pytest.mark.parametrize("use_graph", [True, False])
-def test_batch_equals_solo_mixed_sizes(use_graph):
+@pytest.mark.parametrize("mode", ["graph", "direct", "split"])
+def test_batch_equals_solo_mixed_sizes(mode):
     # sizes of the batched workload plus a ragged one; one member with another CG count
     sizes = [0, 1, 2, 3, 0, 1]
     cases = [kfsynth.config_case(3, i, size_index=s, frames=2) for i, s in enumerate(sizes)]
@@ -59,8 +64,8 @@ def test_batch_equals_solo_mixed_sizes(use_graph):
     cases.append(extra)
     settings = [dict() for _ in cases]
     settings[4] = dict(n_cg=7)
-    say(f"batch mixed: sizes {[(c.W, c.H) for c in cases]}, graph={use_graph}")
-    solo, members, batch = _run_pair(cases, settings, 2, use_graph)
+    say(f"batch mixed: sizes {[(c.W, c.H) for c in cases]}, mode={mode}")
+    solo, members, batch = _run_pair(cases, settings, 2, mode)
     lay = batch.layout()
     say(f"batch layout {lay}")
     for i, (a, b) in enumerate(zip(solo, members)):
@@ -77,7 +82,7 @@ def test_batch_queues_more_teams_than_resident_workgroups():
     cases = [kfsynth.config_case(3, 10 + i, size_index=1, frames=1) for i in range(n)]
     settings = [dict(tiles=(16, 16)) for _ in cases]
     say(f"batch queued: {n} x 320x240 with 16x16 tiles")
-    solo, members, batch = _run_pair(cases, settings, 1, True)
+    solo, members, batch = _run_pair(cases, settings, 1, "graph")
     lay = batch.layout()
     say(f"batch layout {lay}")
     assert lay["max_queue"] >= 2, lay

@@ -161,6 +161,37 @@ def test_solver_parity(c0, precision, mode):
         assert err.max() <= 2e-4 and np.sqrt(np.mean(err ** 2)) <= 2e-5 and abs(st["tau"] - tau_o) <= 2e-5
 
 
+@pytest.mark.parametrize("precision,threads,tiles,variant", [
+    ("f32", 512, (2, 2), "pipelined"), ("f32", 512, (3, 2), "pipelined"), ("f32", 512, (4, 2), "textbook"),
+    ("f32", 1024, (4, 2), "pipelined"), ("f32", 256, (4, 3), "pipelined"), ("f64", 256, (4, 4), "pipelined"),
+    ("f64", 512, (4, 3), "textbook"), ("f64", 1024, (5, 4), "pipelined")])
+def test_solver_tile_shapes(c0, precision, threads, tiles, variant):
+    """Every workgroup size and pixels-per-thread class of the solver against the oracle."""
+    gu.say(f"[solver-shape] config 0 case 0 {precision} {threads} threads tiles {tiles} {variant}")
+    rho, var = _oracle_state(c0)
+    dt = gu.np_map_dtype(precision)
+    rho_in, var_in = rho.astype(dt), var.astype(dt)
+    kf = gu.make_gpu_kf(c0, precision, "line5", 32, n_gn=4, n_cg=20, tiles=tiles, solver_threads=threads,
+                        cg_variant=variant)
+    lay = kf.solver_layout()
+    assert (lay["tiles_x"], lay["tiles_y"], lay["threads"]) == (tiles[0], tiles[1], threads)
+    mdt = gu.map_dtype(precision)
+    kf.import_state(rho=gu.dev(rho_in, mdt), var=gu.dev(var_in, mdt))
+    kf.solve()
+    st = kf.export_state()
+    prior = gu.rounded_priors(c0, precision)
+    semi = gu.oracle_semi(rho_in.astype(np.float64), var_in.astype(np.float64))
+    x_o, tau_o, _ = fusion.gauss_newton(prior.mu, 0.0, prior, semi,
+                                        SolverParams(n_gn=4, n_cg=20, linear_solver="pcg"))
+    err = np.abs(st["x"].cpu().numpy().astype(np.float64) - x_o)
+    gu.say(f"[solver-shape] max|dx| {err.max():.3e} rms {np.sqrt(np.mean(err ** 2)):.3e} "
+           f"dtau {abs(st['tau'] - tau_o):.3e}")
+    if precision == "f64":
+        assert err.max() <= 1e-10 and abs(st["tau"] - tau_o) <= 1e-10
+    else:
+        assert err.max() <= 2e-4 and np.sqrt(np.mean(err ** 2)) <= 2e-5 and abs(st["tau"] - tau_o) <= 2e-5
+
+
 def test_solver_ragged_tiles(c0):
     """Explicit 7 x 5 tiling of 160 x 120 (ragged last column / row of tiles)."""
     gu.say("[solver] config 0 case 0 f64 fixed tiles 7x5")
