@@ -41,8 +41,7 @@ SOLVER_SRC = os.path.join(ROOT, "paper_2207_12244_amd", "csrc", "kf_solve.hip")
 
 WORKLOAD = dict(config=2, W=640, H=480, frames=30, precision="bf16", pattern="sq5x5", n_samples=128,
                 n_gn=10, n_cg=20)
-BATCHED = dict(config=3, keyframes=64, precision="bf16", pattern="line5", n_samples=32, n_gn=10, n_cg=20,
-               solver_threads=512)
+BATCHED = dict(config=3, keyframes=64, precision="bf16", pattern="line5", n_samples=32, n_gn=10, n_cg=20)
 
 
 def solver_bytes_per_frame(N, n_gn, n_cg, word=4):
@@ -106,20 +105,28 @@ def batched_cases(n):
     return cases
 
 
-def cpu_baseline_batched(case, wl):
-    """The FP64 oracle, as it stands, fusing one keyframe of the batch (the first
-    160 x 120 one) with its frame, timed on the host."""
+def cpu_baseline_batched(cases, wl):
+    """The FP64 oracle, as it stands, fusing one keyframe of each size in the
+    batch with its frame (stereo + 10 x 20 PCG), timed on the host."""
     from oracle import OracleKeyframe, SolverParams, StereoParams
-    ok = OracleKeyframe(case.K, case.W, case.H, StereoParams(n_samples=wl["n_samples"], pattern=wl["pattern"]),
-                        SolverParams(n_gn=wl["n_gn"], n_cg=wl["n_cg"], linear_solver="pcg"))
-    ok.set_prior(case.image0, *case.priors.maps(), case.T_wc0)
-    w0, c0 = time.perf_counter(), time.process_time()
-    ok.fuse_frame(case.images[0], case.poses[0])
-    w1, c1 = time.perf_counter(), time.process_time()
-    wall = w1 - w0
-    cores = max(1, int(round((c1 - c0) / wall)))
-    return {"value": round(case.W * case.H / wall / 1e6, 6), "unit": "Mpixel/s", "cores": cores, "kind": "oracle",
-            "sample": f"1 keyframe of the batch ({case.W}x{case.H}) fused with its frame, {wall:.1f} s wall",
+    picked = {}
+    for c in cases:
+        picked.setdefault((c.W, c.H), c)
+    wall = cpu = 0.0
+    px = 0
+    for (W, H), case in sorted(picked.items()):
+        ok = OracleKeyframe(case.K, W, H, StereoParams(n_samples=wl["n_samples"], pattern=wl["pattern"]),
+                            SolverParams(n_gn=wl["n_gn"], n_cg=wl["n_cg"], linear_solver="pcg"))
+        ok.set_prior(case.image0, *case.priors.maps(), case.T_wc0)
+        w0, c0 = time.perf_counter(), time.process_time()
+        ok.fuse_frame(case.images[0], case.poses[0])
+        wall += time.perf_counter() - w0
+        cpu += time.process_time() - c0
+        px += W * H
+    cores = max(1, int(round(cpu / wall)))
+    sizes = ", ".join(f"{W}x{H}" for W, H in sorted(picked))
+    return {"value": round(px / wall / 1e6, 6), "unit": "Mpixel/s", "cores": cores, "kind": "oracle",
+            "sample": f"one keyframe of each size in the batch ({sizes}) fused with its frame, {wall:.1f} s wall",
             "seconds": round(wall, 3)}
 
 
@@ -127,11 +134,17 @@ def run_batched(a, torch, cases):
     """Batched form: one step = one new frame fused into each of 64 keyframes."""
     from paper_2207_12244_amd.kf import Batch, Keyframe
     wl = BATCHED
+    from paper_2207_12244_amd import autotune
     dev = lambda x, dt: torch.as_tensor(np.ascontiguousarray(x), dtype=dt, device="cuda")
+    t_tune = time.perf_counter()
+    pol = autotune.tuned_policy([(c.W, c.H) for c in cases], wl["precision"], wl["n_gn"], wl["n_cg"])
+    print(f"# batched: shape policy {pol['threads']} threads x {pol['ppt']} px/thread "
+          f"({time.perf_counter() - t_tune:.1f}s)", file=sys.stderr, flush=True)
     members, imgs, poses = [], [], []
     for c in cases:
         kf = Keyframe(c.W, c.H, K=c.K, precision=wl["precision"], pattern=wl["pattern"], n_samples=wl["n_samples"],
-                      n_gn=wl["n_gn"], n_cg=wl["n_cg"], solver_threads=wl["solver_threads"])
+                      n_gn=wl["n_gn"], n_cg=wl["n_cg"], solver_threads=pol["threads"],
+                      tiles=autotune.tiles_for(c.W, c.H, pol["threads"], pol["ppt"]))
         kf.set_prior(dev(c.image0, torch.uint8), *[dev(m, torch.float32) for m in c.priors.maps()], c.T_wc0)
         members.append(kf)
         imgs.append(dev(c.images[0], torch.uint8))
@@ -177,7 +190,8 @@ def run_batched(a, torch, cases):
                                f"{wl['n_gn']} GN x {wl['n_cg']} PCG",
                    "sizes": sizes, "pixels_per_step": px,
                    "seeds": f"{kfsynth_seed(wl['config'], 0)}..{kfsynth_seed(wl['config'], len(cases) - 1)}",
-                   "solver_launch": batch.layout()},
+                   "solver_launch": batch.layout(),
+                   "shape_policy": {"threads": pol["threads"], "px_per_thread_cap": pol["ppt"]}},
         "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 4),
                        "p99": round(float(np.percentile(lat_ms, 99)), 4)},
         "stage_ms_per_step": {"stereo": round(float(np.mean(stereo_ms)), 4),
@@ -188,8 +202,7 @@ def run_batched(a, torch, cases):
                      "avg_launch_ms": round(solve_avg_s * 1000.0, 4)},
     }
     if not a.no_cpu_baseline:
-        small = next((c for c in cases if c.W == 160), cases[0])
-        out["cpu_baseline"] = cpu_baseline_batched(small, wl)
+        out["cpu_baseline"] = cpu_baseline_batched(cases, wl)
     batch.close()
     return out
 

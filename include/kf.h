@@ -219,6 +219,14 @@ kf_status kf_batch_create(kf_ctx* const* members, int32_t n, const kf_batch_conf
    reuses (that of the call before last) is still being uploaded. */
 kf_status kf_batch_fuse(kf_batch* batch, const uint8_t* const* images, const double* poses);
 
+/* kf_batch_fuse for a subset: members[0 .. n_active) are distinct member
+   indices (host int32, positions in the array given to kf_batch_create), and
+   images / poses hold one entry per listed member, in that order. Members not
+   listed are left untouched. n_active = 0 is a no-op. This is the call a
+   serving loop makes with whichever streams have a frame ready. */
+kf_status kf_batch_fuse_subset(kf_batch* batch, int32_t n_active, const int32_t* members,
+                               const uint8_t* const* images, const double* poses);
+
 /* The two halves of kf_batch_fuse, for callers that time or interleave them:
    the stereo update of every member (staging + stereo launches), and the
    optimisation of every member (the persistent solver launch). Same

@@ -1,8 +1,11 @@
 // Batched executor: many keyframe contexts, each fused with one new frame, by
 // one staging, one stereo and one persistent solver launch per call. The
-// per-keyframe arguments live in device tables; the per-frame part (image
-// pointer and epipolar constants) is uploaded from double-buffered pinned host
-// memory, and the three launches are replayed from one captured HIP graph.
+// per-keyframe solver arguments live in a static device table; each call
+// uploads (from double-buffered pinned host memory, in one copy) the
+// per-frame part: the active member count, their stereo arguments (image
+// pointer and epipolar constants) and the solver's per-workgroup team queues.
+// The launches read all of it from device memory, so they are captured once
+// as HIP graphs and replayed for any subset of the members.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -14,24 +17,45 @@
 
 using namespace kf;
 
+namespace {
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Per-call region of the batch workspace (uploaded as a whole).
+struct DynLayout {
+  size_t hdr, st, queue, qoff, total;
+};
+
+DynLayout dyn_layout(int n, int members_total) {
+  DynLayout L;
+  size_t off = 0;
+  L.hdr = off; off += 256;
+  L.st = off; off += align256((size_t)n * sizeof(StereoArgs));
+  L.queue = off; off += align256((size_t)members_total * 4);
+  L.qoff = off; off += align256((size_t)(members_total + 1) * 4);
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
 struct kf_batch {
   std::vector<kf_ctx*> m;
   hipStream_t stream = nullptr;
-  hipStream_t capture = nullptr;   // private stream the graph is captured on
+  hipStream_t capture = nullptr;   // private stream the graphs are captured on
   int device = 0;
   int prec = 0, pattern = 0, ns = 0, threads = 0, ppt = 0;
   bool pipelined = false;
   size_t smem = 0;
   int grid = 0;                    // solver workgroups
-  int max_queue = 0;               // longest per-workgroup queue
+  int max_queue = 0;               // longest per-workgroup queue of the last schedule
   int capacity = 0;                // co-resident workgroups of the batched solver
   int stereo_blocks = 0;
   bool use_graph = true;
-  StereoArgs* d_st = nullptr;
-  SolveArgs* d_so = nullptr;
-  int32_t* d_queue = nullptr;
-  int32_t* d_qoff = nullptr;
-  StereoArgs* h_pin[2] = {nullptr, nullptr};
+  DynLayout dl{};
+  char* d_dyn = nullptr;           // device: per-call region
+  SolveArgs* d_so = nullptr;       // device: static solver table
+  char* h_pin[2] = {nullptr, nullptr};
   hipEvent_t ev[2] = {nullptr, nullptr};
   bool ev_used[2] = {false, false};
   int parity = 0;
@@ -52,19 +76,22 @@ struct kf_batch {
     }
     if (capture) (void)hipStreamDestroy(capture);
   }
+
+  const int32_t* d_n() const { return reinterpret_cast<const int32_t*>(d_dyn + dl.hdr); }
+  const StereoArgs* d_st() const { return reinterpret_cast<const StereoArgs*>(d_dyn + dl.st); }
+  const int32_t* d_queue() const { return reinterpret_cast<const int32_t*>(d_dyn + dl.queue); }
+  const int32_t* d_qoff() const { return reinterpret_cast<const int32_t*>(d_dyn + dl.qoff); }
 };
 
 namespace {
-
-size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 kf_status bfail(kf_batch* b, kf_status s, const std::string& msg) {
   if (b) b->err = msg;
   return s;
 }
 
-kf_status bhip(kf_batch* b, hipError_t e, const char* where) {
-  return bfail(b, KF_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+kf_status bhip(kf_batch* b, hipError_t e, const std::string& where) {
+  return bfail(b, KF_ERR_HIP, where + ": " + hipGetErrorString(e));
 }
 
 int total_members(kf_ctx* const* m, int n) {
@@ -73,20 +100,7 @@ int total_members(kf_ctx* const* m, int n) {
   return s;
 }
 
-struct WsLayout {
-  size_t st, so, queue, qoff, total;
-};
-
-WsLayout ws_layout(int n, int members) {
-  WsLayout L;
-  size_t off = 0;
-  L.st = off; off += align256((size_t)n * sizeof(StereoArgs));
-  L.so = off; off += align256((size_t)n * sizeof(SolveArgs));
-  L.queue = off; off += align256((size_t)members * 4);
-  L.qoff = off; off += align256((size_t)(members + 1) * 4);
-  L.total = off;
-  return L;
-}
+size_t static_bytes(int n) { return align256((size_t)n * sizeof(SolveArgs)); }
 
 // Estimated duration of one keyframe's solve (microseconds): the latency
 // model of the single-keyframe tiling choice times the synchronisations.
@@ -96,19 +110,16 @@ double team_cost(const kf_ctx* c) {
   return g.n_gn * (cg + 2.0) * iteration_us(c->tiling);
 }
 
-// List schedule of the teams over `grid` workgroups: teams in order of
-// decreasing cost, each on the members that become free first (ties to the
-// lower workgroup index, which spreads a team evenly over the XCDs because
-// consecutive workgroups of a launch are dispatched to consecutive XCDs).
-// Every workgroup's queue follows the one global team order.
-void schedule(kf_batch* b) {
-  const int n = (int)b->m.size();
-  std::vector<int> order(n);
-  std::vector<double> cost(n);
-  for (int i = 0; i < n; ++i) {
-    order[i] = i;
-    cost[i] = team_cost(b->m[i]);
-  }
+// List schedule of the active teams over the `grid` workgroups: teams in
+// order of decreasing cost, each on the workgroups that become free first
+// (ties to the lower workgroup index, which spreads a team evenly over the
+// XCDs because consecutive workgroups of a launch are dispatched to
+// consecutive XCDs). Every workgroup's queue follows the one global team
+// order, which keeps the launch free of deadlock.
+void schedule(kf_batch* b, const std::vector<int>& active) {
+  std::vector<int> order(active);
+  std::vector<double> cost(b->m.size(), 0.0);
+  for (int c : order) cost[c] = team_cost(b->m[c]);
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
   std::vector<double> avail(b->grid, 0.0);
   std::vector<std::vector<int32_t>> q(b->grid);
@@ -137,19 +148,13 @@ void schedule(kf_batch* b) {
   }
 }
 
-hipError_t enqueue_stereo(kf_batch* b, hipStream_t s) {
-  return launch_stereo_batch(b->prec, b->pattern, b->ns, b->d_st, (int)b->m.size(), b->stereo_blocks, s);
-}
-
-hipError_t enqueue_solve(kf_batch* b, hipStream_t s) {
-  return launch_solve_batch(b->prec, b->threads, b->ppt, b->pipelined, b->d_so, b->d_queue, b->d_qoff, b->grid,
-                            b->smem, s);
-}
-
 hipError_t enqueue(kf_batch* b, int which, hipStream_t s) {
   hipError_t e = hipSuccess;
-  if (which != 2) e = enqueue_stereo(b, s);
-  if (e == hipSuccess && which != 1) e = enqueue_solve(b, s);
+  if (which != 2)
+    e = launch_stereo_batch(b->prec, b->pattern, b->ns, b->d_st(), b->d_n(), (int)b->m.size(), b->stereo_blocks, s);
+  if (e == hipSuccess && which != 1)
+    e = launch_solve_batch(b->prec, b->threads, b->ppt, b->pipelined, b->d_so, b->d_queue(), b->d_qoff(), b->grid,
+                           b->smem, s);
   return e;
 }
 
@@ -170,25 +175,22 @@ hipError_t graph_for(kf_batch* b, int which) {
   return e;
 }
 
-hipError_t run(kf_batch* b, int which) {
-  if (!b->use_graph) return enqueue(b, which, b->stream);
-  hipError_t e = graph_for(b, which);
-  if (e != hipSuccess) return e;
-  return hipGraphLaunch(b->exec[which], b->stream);
-}
-
-// Validates the frame, writes the per-frame descriptors into the free pinned
-// buffer and enqueues their upload.
-kf_status upload_frame(kf_batch* b, const uint8_t* const* images, const double* poses, const char* who) {
-  const int n = (int)b->m.size();
-  if (!images || !poses) return bfail(b, KF_ERR_ARG, std::string(who) + ": NULL images or poses");
-  for (int i = 0; i < n; ++i) {
+// One call: validates, fills the free pinned buffer (active count, stereo
+// arguments, team queues), uploads it, launches sequence `which` (0 fuse,
+// 1 stereo, 2 solve) and advances the members' frame / epoch counters.
+kf_status run_call(kf_batch* b, int which, const std::vector<int>& active, const uint8_t* const* images,
+                   const double* poses, const char* who) {
+  const bool stereo = which != 2, solve = which != 1;
+  for (size_t k = 0; k < active.size(); ++k) {
+    const int i = active[k];
     if (!b->m[i]->has_prior)
       return bfail(b, KF_ERR_STATE, std::string(who) + ": member " + std::to_string(i) + " has no prior (kf_set_prior)");
-    if (!images[i]) return bfail(b, KF_ERR_ARG, std::string(who) + ": NULL image for member " + std::to_string(i));
-    if (!pose_ok(poses + 16 * (size_t)i))
-      return bfail(b, KF_ERR_ARG, std::string(who) + ": pose of member " + std::to_string(i) +
-                                  " must be finite with last row 0 0 0 1");
+    if (stereo) {
+      if (!images[k]) return bfail(b, KF_ERR_ARG, std::string(who) + ": NULL image for member " + std::to_string(i));
+      if (!pose_ok(poses + 16 * k))
+        return bfail(b, KF_ERR_ARG, std::string(who) + ": pose of member " + std::to_string(i) +
+                                    " must be finite with last row 0 0 0 1");
+    }
   }
   // the pinned buffer of this parity was last read by the upload two calls ago
   const int p = b->parity;
@@ -197,39 +199,48 @@ kf_status upload_frame(kf_batch* b, const uint8_t* const* images, const double* 
     e = hipEventSynchronize(b->ev[p]);
     if (e != hipSuccess) return bhip(b, e, who);
   }
-  StereoArgs* h = b->h_pin[p];
-  for (int i = 0; i < n; ++i)
-    if (!stereo_args(b->m[i], images[i], poses + 16 * (size_t)i, &h[i]))
-      return bfail(b, KF_ERR_ARG, std::string(who) + ": singular pose for member " + std::to_string(i));
-  e = hipMemcpyAsync(b->d_st, h, n * sizeof(StereoArgs), hipMemcpyHostToDevice, b->stream);
+  char* h = b->h_pin[p];
+  int32_t* hn = reinterpret_cast<int32_t*>(h + b->dl.hdr);
+  StereoArgs* hst = reinterpret_cast<StereoArgs*>(h + b->dl.st);
+  *hn = stereo ? (int32_t)active.size() : 0;
+  if (stereo)
+    for (size_t k = 0; k < active.size(); ++k)
+      if (!stereo_args(b->m[active[k]], images[k], poses + 16 * k, &hst[k]))
+        return bfail(b, KF_ERR_ARG, std::string(who) + ": singular pose for member " + std::to_string(active[k]));
+  if (solve) {
+    schedule(b, active);
+    std::memcpy(h + b->dl.queue, b->queue.data(), b->queue.size() * 4);
+    std::memcpy(h + b->dl.qoff, b->qoff.data(), b->qoff.size() * 4);
+    for (int i : active) {
+      e = epoch_wrap_if_needed(b->m[i], solve_epoch_bound(b->m[i]->cfg));
+      if (e != hipSuccess) return bhip(b, e, std::string(who) + " (epoch wrap)");
+    }
+  } else {
+    std::memset(h + b->dl.qoff, 0, (size_t)(b->grid + 1) * 4);
+  }
+  e = hipMemcpyAsync(b->d_dyn, h, b->dl.total, hipMemcpyHostToDevice, b->stream);
   if (e == hipSuccess) e = hipEventRecord(b->ev[p], b->stream);
-  if (e != hipSuccess) return bhip(b, e, who);
+  if (e != hipSuccess) return bhip(b, e, std::string(who) + " (descriptor upload)");
   b->ev_used[p] = true;
   b->parity ^= 1;
-  return KF_OK;
-}
-
-kf_status check_members(kf_batch* b, const char* who) {
-  for (size_t i = 0; i < b->m.size(); ++i)
-    if (!b->m[i]->has_prior)
-      return bfail(b, KF_ERR_STATE, std::string(who) + ": member " + std::to_string(i) + " has no prior (kf_set_prior)");
-  return KF_OK;
-}
-
-kf_status pre_solve(kf_batch* b, const char* who) {
-  for (kf_ctx* c : b->m) {
-    const hipError_t e = epoch_wrap_if_needed(c, solve_epoch_bound(c->cfg));
-    if (e != hipSuccess) return bhip(b, e, who);
+  if (b->use_graph) {
+    e = graph_for(b, which);
+    if (e == hipSuccess) e = hipGraphLaunch(b->exec[which], b->stream);
+  } else {
+    e = enqueue(b, which, b->stream);
+  }
+  if (e != hipSuccess) return bhip(b, e, who);
+  for (int i : active) {
+    if (stereo) ++b->m[i]->frame;
+    if (solve) b->m[i]->epoch += solve_epoch_bound(b->m[i]->cfg);
   }
   return KF_OK;
 }
 
-void post_solve(kf_batch* b) {
-  for (kf_ctx* c : b->m) c->epoch += solve_epoch_bound(c->cfg);
-}
-
-void post_stereo(kf_batch* b) {
-  for (kf_ctx* c : b->m) ++c->frame;
+std::vector<int> all_members(const kf_batch* b) {
+  std::vector<int> v(b->m.size());
+  for (size_t i = 0; i < v.size(); ++i) v[i] = (int)i;
+  return v;
 }
 
 }  // namespace
@@ -246,7 +257,7 @@ size_t kf_batch_workspace_bytes(kf_ctx* const* members, int32_t n) {
   if (!members || n < 1 || n > KF_BATCH_MAX) return 0;
   for (int i = 0; i < n; ++i)
     if (!members[i]) return 0;
-  return ws_layout(n, total_members(members, n)).total;
+  return static_bytes(n) + dyn_layout(n, total_members(members, n)).total;
 }
 
 kf_status kf_batch_create(kf_ctx* const* members, int32_t n, const kf_batch_config* cfg, kf_batch** out) {
@@ -269,9 +280,9 @@ kf_status kf_batch_create(kf_ctx* const* members, int32_t n, const kf_batch_conf
       return KF_ERR_ARG;
   }
   const int members_total = total_members(members, n);
-  const WsLayout L = ws_layout(n, members_total);
+  const DynLayout dl = dyn_layout(n, members_total);
   if (!cfg->workspace) return KF_ERR_ARG;
-  if (cfg->workspace_bytes < L.total) return KF_ERR_OOM;
+  if (cfg->workspace_bytes < static_bytes(n) + dl.total) return KF_ERR_OOM;
   if (reinterpret_cast<uintptr_t>(cfg->workspace) % 256 != 0) return KF_ERR_ARG;
 
   kf_batch* b = new (std::nothrow) kf_batch();
@@ -286,51 +297,52 @@ kf_status kf_batch_create(kf_ctx* const* members, int32_t n, const kf_batch_conf
   b->pipelined = solve_pipelined(c0->cfg);
   b->use_graph = cfg->use_graph != 0;
   b->stereo_blocks = c0->stereo_blocks;
+  b->dl = dl;
   char* ws = reinterpret_cast<char*>(cfg->workspace);
-  b->d_st = reinterpret_cast<StereoArgs*>(ws + L.st);
-  b->d_so = reinterpret_cast<SolveArgs*>(ws + L.so);
-  b->d_queue = reinterpret_cast<int32_t*>(ws + L.queue);
-  b->d_qoff = reinterpret_cast<int32_t*>(ws + L.qoff);
+  b->d_so = reinterpret_cast<SolveArgs*>(ws);
+  b->d_dyn = ws + static_bytes(n);
 
-  int maxB = 0, maxw = 0, maxh = 0;
+  int maxB = 0;
+  size_t smem = 0;
   for (kf_ctx* c : b->m) {
     b->ppt = std::max(b->ppt, c->tiling.ppt);
     maxB = std::max(maxB, c->tiling.blocks);
-    maxw = std::max(maxw, c->tiling.tile_w);
-    maxh = std::max(maxh, c->tiling.tile_h);
+    smem = std::max(smem, solve_smem_bytes(b->prec, c->tiling));
   }
   if (!solve_batch_supported(b->prec, b->threads, b->ppt)) {
     delete b;
     return KF_ERR_ARG;
   }
-  // LDS: room for the largest team's partials and the largest tile's rings
-  b->smem = solve_batch_smem_bytes(b->prec, b->threads, maxB, maxw, maxh);
+  // LDS: the largest member's need (team partials + the three rings of its tile)
+  b->smem = smem;
   b->capacity = solve_batch_coresident(b->prec, b->threads, b->ppt, b->pipelined, b->smem, b->device);
   if (b->capacity < maxB) {
     delete b;
     return KF_ERR_ARG;
   }
   b->grid = std::min(b->capacity, members_total);
-  schedule(b);
+  schedule(b, all_members(b));
+  const int full_queue = b->max_queue;
 
   std::vector<SolveArgs> so(n);
   for (int i = 0; i < n; ++i) {
     solve_args(b->m[i], &so[i]);
     // a member may wait for its team while the team's other members finish
     // the teams queued before it
-    so[i].timeout_ticks = b->m[i]->timeout_ticks * (uint64_t)b->max_queue;
+    so[i].timeout_ticks = b->m[i]->timeout_ticks * (uint64_t)full_queue;
   }
   hipError_t e = hipMemcpy(b->d_so, so.data(), n * sizeof(SolveArgs), hipMemcpyHostToDevice);
-  if (e == hipSuccess)
-    e = hipMemcpy(b->d_queue, b->queue.data(), b->queue.size() * 4, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(b->d_qoff, b->qoff.data(), b->qoff.size() * 4, hipMemcpyHostToDevice);
   for (int i = 0; i < 2 && e == hipSuccess; ++i) {
-    e = hipHostMalloc(reinterpret_cast<void**>(&b->h_pin[i]), n * sizeof(StereoArgs), hipHostMallocDefault);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev[i], hipEventDisableTiming);
+    e = hipHostMalloc(reinterpret_cast<void**>(&b->h_pin[i]), dl.total, hipHostMallocDefault);
+    if (e == hipSuccess) {
+      std::memset(b->h_pin[i], 0, dl.total);
+      e = hipEventCreateWithFlags(&b->ev[i], hipEventDisableTiming);
+    }
   }
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
   if (e == hipSuccess && b->use_graph) e = graph_for(b, 0);
   if (e != hipSuccess) {
+    (void)hipGetLastError();
     delete b;
     return KF_ERR_HIP;
   }
@@ -356,35 +368,36 @@ kf_status kf_batch_layout(const kf_batch* b, int32_t out[4]) {
 
 kf_status kf_batch_fuse(kf_batch* b, const uint8_t* const* images, const double* poses) {
   if (!b) return KF_ERR_ARG;
-  kf_status s = upload_frame(b, images, poses, "kf_batch_fuse");
-  if (s == KF_OK) s = pre_solve(b, "kf_batch_fuse");
-  if (s != KF_OK) return s;
-  const hipError_t e = run(b, 0);
-  if (e != hipSuccess) return bhip(b, e, "kf_batch_fuse");
-  post_stereo(b);
-  post_solve(b);
-  return KF_OK;
+  if (!images || !poses) return bfail(b, KF_ERR_ARG, "kf_batch_fuse: NULL images or poses");
+  return run_call(b, 0, all_members(b), images, poses, "kf_batch_fuse");
+}
+
+kf_status kf_batch_fuse_subset(kf_batch* b, int32_t n_active, const int32_t* members, const uint8_t* const* images,
+                               const double* poses) {
+  if (!b) return KF_ERR_ARG;
+  if (n_active < 0 || n_active > (int32_t)b->m.size())
+    return bfail(b, KF_ERR_ARG, "kf_batch_fuse_subset: n_active out of range");
+  if (n_active == 0) return KF_OK;
+  if (!members || !images || !poses) return bfail(b, KF_ERR_ARG, "kf_batch_fuse_subset: NULL argument");
+  std::vector<int> active(members, members + n_active);
+  std::vector<char> seen(b->m.size(), 0);
+  for (int i : active) {
+    if (i < 0 || i >= (int)b->m.size() || seen[i])
+      return bfail(b, KF_ERR_ARG, "kf_batch_fuse_subset: member indices must be distinct and in range");
+    seen[i] = 1;
+  }
+  return run_call(b, 0, active, images, poses, "kf_batch_fuse_subset");
 }
 
 kf_status kf_batch_stereo_update(kf_batch* b, const uint8_t* const* images, const double* poses) {
   if (!b) return KF_ERR_ARG;
-  const kf_status s = upload_frame(b, images, poses, "kf_batch_stereo_update");
-  if (s != KF_OK) return s;
-  const hipError_t e = run(b, 1);
-  if (e != hipSuccess) return bhip(b, e, "kf_batch_stereo_update");
-  post_stereo(b);
-  return KF_OK;
+  if (!images || !poses) return bfail(b, KF_ERR_ARG, "kf_batch_stereo_update: NULL images or poses");
+  return run_call(b, 1, all_members(b), images, poses, "kf_batch_stereo_update");
 }
 
 kf_status kf_batch_solve(kf_batch* b) {
   if (!b) return KF_ERR_ARG;
-  kf_status s = check_members(b, "kf_batch_solve");
-  if (s == KF_OK) s = pre_solve(b, "kf_batch_solve");
-  if (s != KF_OK) return s;
-  const hipError_t e = run(b, 2);
-  if (e != hipSuccess) return bhip(b, e, "kf_batch_solve");
-  post_solve(b);
-  return KF_OK;
+  return run_call(b, 2, all_members(b), nullptr, nullptr, "kf_batch_solve");
 }
 
 }  // extern "C"

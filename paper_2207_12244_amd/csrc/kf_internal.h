@@ -11,6 +11,19 @@
 
 namespace kf {
 
+// Global address space. Pointers loaded from memory (argument tables) are
+// generic to the compiler, which then emits flat instructions: those also
+// count against the LDS wait counter, so every LDS wait would drain the
+// outstanding global accesses too. Kernels convert their buffer pointers once.
+// (The qualifier only exists in the device pass of the single-source build.)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define KF_GLOBAL __attribute__((address_space(1)))
+#else
+#define KF_GLOBAL
+#endif
+template <typename P>
+__device__ inline KF_GLOBAL P* gp(P* p) { return (KF_GLOBAL P*)p; }
+
 // ------------------------------------------------------------------ storage types
 
 // bfloat16 stored as its 16 raw bits; conversions round to nearest even.
@@ -42,6 +55,11 @@ template <typename TI, typename T> __device__ inline T load_img(const TI* p, siz
 template <> __device__ inline double load_img<double, double>(const double* p, size_t i) { return p[i]; }
 template <> __device__ inline float load_img<float, float>(const float* p, size_t i) { return p[i]; }
 template <> __device__ inline float load_img<bf16, float>(const bf16* p, size_t i) { return bf16_to_float(p[i]); }
+
+// Value of one stored image element in the arithmetic type.
+__device__ inline double img_value(double v) { return v; }
+__device__ inline float img_value(float v) { return v; }
+__device__ inline float img_value(bf16 v) { return bf16_to_float(v); }
 
 template <typename TI, typename T> __device__ inline TI to_img(T v);
 template <> __device__ inline double to_img<double, double>(double v) { return v; }
@@ -173,8 +191,10 @@ struct ImportArgs {
 
 hipError_t launch_prior(int prec, const PriorArgs& a, hipStream_t s);
 hipError_t launch_stereo(int prec, int pattern, int ns, const StereoArgs& a, int blocks, hipStream_t s);
-hipError_t launch_stereo_batch(int prec, int pattern, int ns, const StereoArgs* tab, int n, int blocks,
-                               hipStream_t s);
+// Batched stereo: the active count *n (device, <= nmax) and the table entries
+// are read by the kernels, so the launches can be captured once.
+hipError_t launch_stereo_batch(int prec, int pattern, int ns, const StereoArgs* tab, const int32_t* n, int nmax,
+                               int blocks, hipStream_t s);
 hipError_t launch_solve(int prec, const Tiling& t, const SolveArgs& a, bool cooperative, bool pipelined,
                         hipStream_t s);
 // Batched solver: workgroup g runs the team members queue[qoff[g] .. qoff[g+1])
@@ -182,7 +202,6 @@ hipError_t launch_solve(int prec, const Tiling& t, const SolveArgs& a, bool coop
 // co-resident.
 hipError_t launch_solve_batch(int prec, int threads, int ppt, bool pipelined, const SolveArgs* tab,
                               const int32_t* queue, const int32_t* qoff, int grid, size_t smem, hipStream_t s);
-size_t solve_batch_smem_bytes(int prec, int threads, int team_blocks, int tile_w, int tile_h);
 int solve_batch_coresident(int prec, int threads, int ppt, bool pipelined, size_t smem, int device);
 bool solve_batch_supported(int prec, int threads, int ppt);
 hipError_t launch_read(int prec, const ReadArgs& a, hipStream_t s);

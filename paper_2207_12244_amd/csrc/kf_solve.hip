@@ -26,11 +26,11 @@ namespace {
 
 constexpr int GMAX = 2;      // ghost slots per thread: ghost ring <= GMAX * threads cells
 
-__device__ inline void st_word(uint64_t* p, uint64_t v) {
+__device__ inline void st_word(KF_GLOBAL uint64_t* p, uint64_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ inline uint64_t ld_word(const uint64_t* p) {
-  return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+__device__ inline uint64_t ld_word(const KF_GLOBAL uint64_t* p) {
+  return __hip_atomic_load(const_cast<KF_GLOBAL uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 // Compiler-only barrier (no instruction): the value counts as redefined here,
 // so per-pixel addresses derived from it are recomputed inside the loop that
@@ -43,7 +43,7 @@ __device__ inline uint64_t tagged(uint32_t bits, uint32_t e) { return ((uint64_t
 template <typename V> struct Wire;
 template <> struct Wire<float> {
   static constexpr int N = 1;
-  __device__ static void put(uint64_t* w, float v, uint32_t e) { st_word(w, tagged(__float_as_uint(v), e)); }
+  __device__ static void put(KF_GLOBAL uint64_t* w, float v, uint32_t e) { st_word(w, tagged(__float_as_uint(v), e)); }
   __device__ static float make(uint32_t lo, uint32_t) { return __uint_as_float(lo); }
 };
 // One-word transport of an FP64 partial: the top 48 bits of the double
@@ -63,7 +63,7 @@ struct Packed48 {
 
 template <> struct Wire<double> {
   static constexpr int N = 2;
-  __device__ static void put(uint64_t* w, double v, uint32_t e) {
+  __device__ static void put(KF_GLOBAL uint64_t* w, double v, uint32_t e) {
     const uint64_t bits = (uint64_t)__double_as_longlong(v);
     st_word(w, tagged((uint32_t)bits, e));
     st_word(w + 1, tagged((uint32_t)(bits >> 32), e));
@@ -118,9 +118,9 @@ struct Team {
   static constexpr int PSLOTS = (NV_MAX * MAX_TEAM + NT - 1) / NT;   // partial slots polled per thread
   int B, b, tw, th, rw, perim, tile_w, tile_h;
   int nb_up, nb_dn, nb_lf, nb_rt;
-  uint64_t* parts;
-  uint64_t* halo;
-  int32_t* err;
+  KF_GLOBAL uint64_t* parts;
+  KF_GLOBAL uint64_t* halo;
+  KF_GLOBAL int32_t* err;
   uint64_t limit;
   bool packed;      // one-word partials (Packed48) instead of two words
   double* s_wred;   // [NW][NV_MAX]
@@ -131,10 +131,10 @@ struct Team {
   int g_off[GMAX];  // offset in its boundary list
   int g_li[GMAX];   // ring index
 
-  __device__ uint64_t* part_slot(uint32_t e, int v, int j) const {
+  __device__ KF_GLOBAL uint64_t* part_slot(uint32_t e, int v, int j) const {
     return parts + ((size_t)((e & 1u) * NV_MAX + v) * B + j) * 2;
   }
-  __device__ uint64_t* halo_slot(uint32_t e, int blk, int off) const {
+  __device__ KF_GLOBAL uint64_t* halo_slot(uint32_t e, int blk, int off) const {
     return halo + ((size_t)((e & 1u) * B + blk) * perim + off) * 2;
   }
 
@@ -187,7 +187,7 @@ struct Team {
       for (int q = 0; q < PSLOTS; ++q) {
         if (!p_ready[q]) {
           const int s = tid + q * NT, v = s / B, j = s - v * B;
-          const uint64_t* w = part_slot(e, v, j);
+          const KF_GLOBAL uint64_t* w = part_slot(e, v, j);
           pw0[q] = ld_word(w);
           if (!packed) pw1[q] = ld_word(w + 1);
         }
@@ -195,7 +195,7 @@ struct Team {
 #pragma unroll
       for (int m = 0; m < GMAX; ++m) {
         if (!g_ready[m]) {
-          const uint64_t* w = halo_slot(e, g_src[m], g_off[m]);
+          const KF_GLOBAL uint64_t* w = halo_slot(e, g_src[m], g_off[m]);
           gw0[m] = ld_word(w);
           if (Wire<T>::N == 2) gw1[m] = ld_word(w + 1);
         }
@@ -239,7 +239,7 @@ struct Team {
     }
     if (!ok) {
       *s_abort = 1;
-      atomicOr(err, ERR_TIMEOUT);
+      __hip_atomic_fetch_or(err, ERR_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
     if (*s_abort) return false;
@@ -277,9 +277,10 @@ __device__ __forceinline__ void solve_member(const SolveArgs& a, const int b, un
   tm.nb_dn = by < a.tiles_y - 1 ? b + a.tiles_x : -1;
   tm.nb_lf = bx > 0 ? b - 1 : -1;
   tm.nb_rt = bx < a.tiles_x - 1 ? b + 1 : -1;
-  tm.parts = a.parts;
-  tm.halo = a.halo;
-  tm.err = &a.scal->err;
+  KF_GLOBAL DevScalars* scal = gp(a.scal);
+  tm.parts = gp(a.parts);
+  tm.halo = gp(a.halo);
+  tm.err = &scal->err;
   tm.limit = a.timeout_ticks;
   tm.packed = a.packed != 0;
   // LDS: [NW][NV_MAX] wave partials, [NV_MAX][B] team partials, abort flag,
@@ -325,16 +326,16 @@ __device__ __forceinline__ void solve_member(const SolveArgs& a, const int b, un
   }
   __syncthreads();
 
-  const T* pr = static_cast<const T*>(a.prior);
-  const T* mu_g = pr;
-  const T* isn_g = pr + (size_t)N;
-  const T* gx_g = pr + 2 * (size_t)N;
-  const T* isgx_g = pr + 3 * (size_t)N;
-  const T* gy_g = pr + 4 * (size_t)N;
-  const T* isgy_g = pr + 5 * (size_t)N;
-  T* x_g = static_cast<T*>(a.x);
-  const T* rho_g = static_cast<const T*>(a.rho);
-  const T* var_g = static_cast<const T*>(a.var);
+  const KF_GLOBAL T* pr = gp(static_cast<const T*>(a.prior));
+  const KF_GLOBAL T* mu_g = pr;
+  const KF_GLOBAL T* isn_g = pr + (size_t)N;
+  const KF_GLOBAL T* gx_g = pr + 2 * (size_t)N;
+  const KF_GLOBAL T* isgx_g = pr + 3 * (size_t)N;
+  const KF_GLOBAL T* gy_g = pr + 4 * (size_t)N;
+  const KF_GLOBAL T* isgy_g = pr + 5 * (size_t)N;
+  KF_GLOBAL T* x_g = gp(static_cast<T*>(a.x));
+  const KF_GLOBAL T* rho_g = gp(static_cast<const T*>(a.rho));
+  const KF_GLOBAL T* var_g = gp(static_cast<const T*>(a.var));
 
   // per-pixel registers; pixel j of this thread is k = tid + j NT of the tile
   int lxy[PPT];   // (ly << 16) | lx, or -1 when the thread has no j-th pixel
@@ -363,12 +364,12 @@ __device__ __forceinline__ void solve_member(const SolveArgs& a, const int b, un
       xs[li_g] = x_g[(oy + gy_) * W + ox + gx_];
     }
   }
-  double tau = a.scal->tau;
+  double tau = scal->tau;
   __syncthreads();
 
   // epoch base of this launch: written by the previous launch's workgroup 0
   // after its team finished, so every workgroup here reads the same value
-  const uint32_t e0 = a.scal->epoch;
+  const uint32_t e0 = scal->epoch;
   uint32_t e = e0;
   const bool tol_mode = a.cg_rtol > 0.0;
   const int limit = tol_mode ? a.cg_max : a.n_cg;
@@ -623,11 +624,11 @@ __device__ __forceinline__ void solve_member(const SolveArgs& a, const int b, un
   if (b == 0 && tid == 0) {
     // every member has read e0 before its first publish, and workgroup 0
     // passed the last synchronisation, so no member still needs the old base
-    a.scal->epoch = e0 + a.epoch_span;
-    a.scal->tau = tau;
-    a.scal->cg_iterations = cg_total;
-    a.scal->cg_rel_residual = relres;
-    a.scal->n_valid = (int32_t)n_valid;
+    scal->epoch = e0 + a.epoch_span;
+    scal->tau = tau;
+    scal->cg_iterations = cg_total;
+    scal->cg_rel_residual = relres;
+    scal->n_valid = (int32_t)n_valid;
   }
 }
 
@@ -719,16 +720,25 @@ hipError_t solve_t(const Tiling& t, const SolveArgs& a, bool cooperative, bool p
 
 size_t solve_smem_bytes(int prec, const Tiling& t) { return smem_for(prec == KF_F64 ? 8 : 4, t); }
 
+// Workgroups of kernel fn the device holds at once with `smem` bytes of LDS
+// each; 0 (and the runtime's error state cleared) if a query fails.
+int coresident_of(const void* fn, int threads, size_t smem, int device) {
+  int per_cu = 0, cus = 0;
+  hipError_t e = hipSuccess;
+  if (smem > 48 * 1024) e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, smem);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return per_cu * cus;
+}
+
 int solve_max_coresident(int prec, const Tiling& t, bool pipelined, int device) {
   const void* fn = prec == KF_F64 ? solve_fn<double>(t, pipelined) : solve_fn<float>(t, pipelined);
   if (!fn) return 0;
-  const size_t sm = solve_smem_bytes(prec, t);
-  if (sm > 48 * 1024 && hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm) != hipSuccess)
-    return 0;
-  int per_cu = 0, cus = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, t.threads, sm) != hipSuccess) return 0;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
-  return per_cu * cus;
+  return coresident_of(fn, t.threads, solve_smem_bytes(prec, t), device);
 }
 
 hipError_t launch_solve(int prec, const Tiling& t, const SolveArgs& a, bool cooperative, bool pipelined,
@@ -737,26 +747,12 @@ hipError_t launch_solve(int prec, const Tiling& t, const SolveArgs& a, bool coop
   return solve_t<float>(t, a, cooperative, pipelined, s);
 }
 
-size_t solve_batch_smem_bytes(int prec, int threads, int team_blocks, int tile_w, int tile_h) {
-  Tiling t{};
-  t.threads = threads;
-  t.blocks = team_blocks;
-  t.tile_w = tile_w;
-  t.tile_h = tile_h;
-  return smem_for(prec == KF_F64 ? 8 : 4, t);
-}
-
 bool solve_batch_supported(int prec, int threads, int ppt) { return batch_fn(prec, threads, ppt, true) != nullptr; }
 
 int solve_batch_coresident(int prec, int threads, int ppt, bool pipelined, size_t smem, int device) {
   const void* fn = batch_fn(prec, threads, ppt, pipelined);
   if (!fn) return 0;
-  if (smem > 48 * 1024 && hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess)
-    return 0;
-  int per_cu = 0, cus = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, smem) != hipSuccess) return 0;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
-  return per_cu * cus;
+  return coresident_of(fn, threads, smem, device);
 }
 
 hipError_t launch_solve_batch(int prec, int threads, int ppt, bool pipelined, const SolveArgs* tab,

@@ -1,11 +1,12 @@
 // Semi-dense estimation (Sec. II-B): epipolar SSD search, interpolation between
 // two steps, variance of eq. (semi), inverse-depth Gaussian filter.
 //
-// Work mapping: a group of G = min(N_s, 64) lanes of one wavefront handles one
-// textured keyframe pixel; lane l evaluates samples k = l, l + G, ... The
-// keyframe pattern (5 or 25 values) is staged once per pixel in LDS and read
-// by every lane as a broadcast; the argmin over the N_s SSDs is a butterfly of
-// cross-lane shuffles inside the group with ties resolved to the smaller k.
+// Work mapping: a group of G lanes of one wavefront (lanes_per_pixel) handles
+// one textured keyframe pixel; lane l of the group evaluates samples k = l,
+// l + G, ... The keyframe pattern (5 or 25 values) is evaluated once per pixel
+// and handed to every lane of the group by cross-lane broadcasts; the argmin
+// over the N_s SSDs is a butterfly of cross-lane shuffles inside the group
+// with ties resolved to the smaller k. No LDS, no barriers.
 #include "kf_internal.h"
 
 namespace kf {
@@ -14,6 +15,18 @@ namespace {
 
 constexpr int ST_THREADS = 256;
 constexpr int ST_WAVES = ST_THREADS / 64;
+
+// Lanes of a wavefront that share one textured pixel: about 4 samples per
+// lane, so that the per-pixel work (geometry, argmin, sub-pixel step, filter),
+// which every lane of the group repeats, is spread over several pixels per
+// wavefront; at least 32 lanes for the 25-point pattern, so that each of its
+// points is evaluated by one lane and broadcast. Any split gives the same
+// result (the argmin is a lexicographic (SSD, k) minimum).
+constexpr int lanes_per_pixel(int pat, int ns) {
+  int g = ns / 4 < 1 ? 1 : (ns / 4 > 64 ? 64 : ns / 4);
+  if (pat == KF_PAT_SQ5X5 && g < 32) g = ns < 32 ? ns : 32;
+  return g;
+}
 
 template <typename T>
 struct PixelGeom {
@@ -26,10 +39,22 @@ struct PixelGeom {
   bool ok;
 };
 
+// Two consecutive uint8 taps at byte address p of the staged frame from the
+// two aligned dwords that hold them (rows are padded by >= 8 bytes, so the
+// second dword is in bounds) and one byte-align.
+template <typename T>
+__device__ inline void tap_pair(const KF_GLOBAL uint8_t* p, T& t0, T& t1) {
+  const uintptr_t a = (uintptr_t)p;
+  const KF_GLOBAL uint32_t* w = (const KF_GLOBAL uint32_t*)(a & ~(uintptr_t)3);
+  const uint32_t v = __builtin_amdgcn_alignbyte(w[1], w[0], (uint32_t)(a & 3u));
+  t0 = (T)(v & 0xffu);
+  t1 = (T)((v >> 8) & 0xffu);
+}
+
 // Bilinear intensity of the staged new frame (uint8, row stride `st`) at
 // (u, v), 0 <= u <= W-1, 0 <= v <= H-1.
 template <typename T>
-__device__ inline T bilin_u8(const uint8_t* img, int st, int W, int H, T u, T v) {
+__device__ inline T bilin_u8(const KF_GLOBAL uint8_t* img, int st, int W, int H, T u, T v) {
   T fu = floor(u), fv = floor(v);
   fu = fu < (T)(W - 2) ? fu : (T)(W - 2);
   fv = fv < (T)(H - 2) ? fv : (T)(H - 2);
@@ -37,7 +62,9 @@ __device__ inline T bilin_u8(const uint8_t* img, int st, int W, int H, T u, T v)
   fv = fv > (T)0 ? fv : (T)0;
   const T f = u - fu, g = v - fv;
   const size_t i = (size_t)(int)fv * st + (int)fu;
-  const T i00 = (T)img[i], i10 = (T)img[i + 1], i01 = (T)img[i + st], i11 = (T)img[i + st + 1];
+  T i00, i10, i01, i11;
+  tap_pair<T>(img + i, i00, i10);
+  tap_pair<T>(img + i + st, i01, i11);
   const T top = i00 + f * (i10 - i00);
   const T bot = i01 + f * (i11 - i01);
   return top + g * (bot - top);
@@ -47,9 +74,9 @@ __device__ inline T bilin_u8(const uint8_t* img, int st, int W, int H, T u, T v)
 // (rows are padded, so reading up to 8 bytes past a row's last pixel is in
 // bounds): three aligned dword loads and two byte-aligns.
 template <typename T>
-__device__ inline void taps6(const uint8_t* p, T* t) {
-  const uintptr_t a = reinterpret_cast<uintptr_t>(p);
-  const uint32_t* w = reinterpret_cast<const uint32_t*>(a & ~(uintptr_t)3);
+__device__ inline void taps6(const KF_GLOBAL uint8_t* p, T* t) {
+  const uintptr_t a = (uintptr_t)p;
+  const KF_GLOBAL uint32_t* w = (const KF_GLOBAL uint32_t*)(a & ~(uintptr_t)3);
   const uint32_t sh = (uint32_t)(a & 3u);
   const uint32_t w0 = w[0], w1 = w[1], w2 = w[2];
   const uint32_t lo = __builtin_amdgcn_alignbyte(w1, w0, sh);
@@ -64,7 +91,7 @@ __device__ inline void taps6(const uint8_t* p, T* t) {
 
 // Same for the resident keyframe image (storage type TI).
 template <typename T, typename TI>
-__device__ inline T bilin_kf(const TI* img, int W, int H, T u, T v) {
+__device__ inline T bilin_kf(const KF_GLOBAL TI* img, int W, int H, T u, T v) {
   T fu = floor(u), fv = floor(v);
   fu = fu < (T)(W - 2) ? fu : (T)(W - 2);
   fv = fv < (T)(H - 2) ? fv : (T)(H - 2);
@@ -72,8 +99,8 @@ __device__ inline T bilin_kf(const TI* img, int W, int H, T u, T v) {
   fv = fv > (T)0 ? fv : (T)0;
   const T f = u - fu, g = v - fv;
   const size_t i = (size_t)(int)fv * W + (int)fu;
-  const T i00 = load_img<TI, T>(img, i), i10 = load_img<TI, T>(img, i + 1);
-  const T i01 = load_img<TI, T>(img, i + W), i11 = load_img<TI, T>(img, i + W + 1);
+  const T i00 = img_value(img[i]), i10 = img_value(img[i + 1]);
+  const T i01 = img_value(img[i + W]), i11 = img_value(img[i + W + 1]);
   const T top = i00 + f * (i10 - i00);
   const T bot = i01 + f * (i11 - i01);
   return top + g * (bot - top);
@@ -174,20 +201,20 @@ __device__ inline T point_residual(const StereoArgs& a, const PixelGeom<T>& g, T
     tu = px + (T)(j % 5 - 2);
     tv = py + (T)(j / 5 - 2);
   }
-  return bilin_u8<T>(a.i1s, a.i1_stride, a.W, a.H, tu, tv) - pat_j;
+  return bilin_u8<T>(gp(a.i1s), a.i1_stride, a.W, a.H, tu, tv) - pat_j;
 }
 
 // Keyframe pattern value of point j at pixel (u, v), rounded to the patch storage type.
 // Textured pixels lie >= 2 px inside the image, so every point is in bounds.
 template <typename T, typename TI, int PAT>
-__device__ inline T kf_point(const TI* i0, int W, int H, T u, T v, const PixelGeom<T>& g, int j) {
+__device__ inline T kf_point(const KF_GLOBAL TI* i0, int W, int H, T u, T v, const PixelGeom<T>& g, int j) {
   T val;
   if (PAT == KF_PAT_LINE5) {
     const T jj = (T)(j - 2);
     val = bilin_kf<T, TI>(i0, W, H, u + jj * g.l0x, v + jj * g.l0y);
   } else {
     const int iu = (int)u + (j % 5 - 2), iv = (int)v + (j / 5 - 2);
-    val = load_img<TI, T>(i0, (size_t)iv * W + iu);
+    val = img_value(i0[(size_t)iv * W + iu]);
   }
   return round_to_img<TI, T>(val);
 }
@@ -214,19 +241,19 @@ __device__ inline T shfl_t(T v, int src) { return __shfl(v, src, 64); }
 // Returns true if the group's lane 0 wrote a new filter estimate.
 template <typename T, typename TI, int PAT, int NS>
 __device__ inline bool stereo_pixel(const StereoArgs& a, int idx, bool active, int lane) {
-  constexpr int G = NS < 64 ? NS : 64;    // lanes per pixel
+  constexpr int G = lanes_per_pixel(PAT, NS);
   constexpr int S = NS / G;                // samples per lane
   constexpr int P = PAT == KF_PAT_LINE5 ? 5 : 25;
   constexpr T INF = (T)INFINITY;
   const int grp = lane / G;
   const int gl = lane % G;
-  const TI* i0 = static_cast<const TI*>(a.i0);
-  T* rho_s = static_cast<T*>(a.rho);
-  T* var_s = static_cast<T*>(a.var);
+  const KF_GLOBAL TI* i0 = gp(static_cast<const TI*>(a.i0));
+  KF_GLOBAL T* rho_s = gp(static_cast<T*>(a.rho));
+  KF_GLOBAL T* var_s = gp(static_cast<T*>(a.var));
   const int W = a.W, H = a.H;
   const int st = a.i1_stride;
   bool updated = false;
-  const int pix = active ? a.list[idx] : 0;
+  const int pix = active ? gp(a.list)[idx] : 0;
   const T u = (T)(pix % W), v = (T)(pix / W);
   const T rho0 = rho_s[pix], var0 = var_s[pix];
   const bool has = var0 > (T)0;
@@ -281,7 +308,7 @@ __device__ inline bool stereo_pixel(const StereoArgs& a, int idx, bool active, i
         const T f = px - fpx, gg = py - fpy;
         const int c0 = (int)fpx - 2, r0 = (int)fpy - 2;
         T hprev[5];
-        const uint8_t* base = a.i1s + (size_t)r0 * st + c0;
+        const KF_GLOBAL uint8_t* base = gp(a.i1s) + (size_t)r0 * st + c0;
 #pragma unroll
         for (int n = 0; n < 6; ++n) {
           // rows and the 6th column may reach one pad row / byte (weight 0 there)
@@ -367,7 +394,7 @@ __device__ inline bool stereo_pixel(const StereoArgs& a, int idx, bool active, i
     sum_dd += shfl_xor_t(sum_dd, m);
   }
   if (gl == 0 && active) {
-    a.match[pix] = (g.ok && best < INF) ? kstar : -1;
+    gp(a.match)[pix] = (g.ok && best < INF) ? kstar : -1;
     if (has_nb && sum_dd > (T)0) {
       T lam = -sum_kd / sum_dd;
       lam = lam < (T)0 ? (T)0 : (lam > (T)1 ? (T)1 : lam);
@@ -397,12 +424,12 @@ __device__ inline bool stereo_pixel(const StereoArgs& a, int idx, bool active, i
 
 template <typename T, typename TI, int PAT, int NS>
 __global__ __launch_bounds__(ST_THREADS) void k_stereo(StereoArgs a) {
-  constexpr int G = NS < 64 ? NS : 64;
+  constexpr int G = lanes_per_pixel(PAT, NS);
   constexpr int GPW = 64 / G;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int grp = lane / G;
-  const int count = a.scal_ro->mask_count;
+  const int count = gp(a.scal_ro)->mask_count;
   const int groups_per_block = ST_WAVES * GPW;
   const int ngroups = gridDim.x * groups_per_block;
   const int my_group = blockIdx.x * groups_per_block + wave * GPW + grp;
@@ -415,7 +442,7 @@ __global__ __launch_bounds__(ST_THREADS) void k_stereo(StereoArgs a) {
   }
   // one atomic per wavefront
   for (int m = 32; m > 0; m >>= 1) updated_here += __shfl_xor(updated_here, m, 64);
-  if (lane == 0 && updated_here) atomicAdd(&a.scal->n_updated, updated_here);
+  if (lane == 0 && updated_here) atomicAdd(&gp(a.scal)->n_updated, updated_here);
 }
 
 // Prefix sums of n per-keyframe counts in LDS (pref[0] = 0, pref[n] = total).
@@ -443,32 +470,39 @@ __device__ inline int find_keyframe(const int* pref, int n, int item) {
   return lo;
 }
 
-// Batched form: the textured pixels of n keyframes form one item space.
+// Batched form: the textured pixels of n keyframes form one item space of
+// wavefront-sized slots (each keyframe's list padded to whole wavefronts), so
+// a wavefront always works on one keyframe and reads its arguments as
+// wave-uniform (scalar) values.
 template <typename T, typename TI, int PAT, int NS>
-__global__ __launch_bounds__(ST_THREADS) void k_stereo_batch(const StereoArgs* tab, int n) {
-  constexpr int G = NS < 64 ? NS : 64;
+__global__ __launch_bounds__(ST_THREADS) void k_stereo_batch(const StereoArgs* __restrict__ tab,
+                                                             const int32_t* __restrict__ n_dev) {
+  constexpr int G = lanes_per_pixel(PAT, NS);
   constexpr int GPW = 64 / G;
   __shared__ int pref[KF_BATCH_MAX + 1];
   __shared__ int upd[KF_BATCH_MAX];
+  const int n = *n_dev;
   for (int c = threadIdx.x; c < n; c += blockDim.x) upd[c] = 0;
-  block_prefix(n, [&](int c) { return tab[c].scal_ro->mask_count; }, pref);
+  block_prefix(n, [&](int c) { return (gp(tab[c].scal_ro)->mask_count + GPW - 1) / GPW; }, pref);
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int grp = lane / G;
   const int total = pref[n];
-  const int groups_per_block = ST_WAVES * GPW;
-  const int ngroups = gridDim.x * groups_per_block;
-  const int my_group = blockIdx.x * groups_per_block + wave * GPW + grp;
-  const int rounds = (total + ngroups - 1) / ngroups;
+  const int nwaves = gridDim.x * ST_WAVES;
+  const int my_wave = blockIdx.x * ST_WAVES + wave;
+  const int rounds = (total + nwaves - 1) / nwaves;
   for (int r = 0; r < rounds; ++r) {
-    const int item = my_group + r * ngroups;
-    const bool active = item < total;
-    const int c = active ? find_keyframe(pref, n, item) : 0;
-    if (stereo_pixel<T, TI, PAT, NS>(tab[c], active ? item - pref[c] : 0, active, lane)) atomicAdd(&upd[c], 1);
+    const int witem = my_wave + r * nwaves;
+    const bool wactive = witem < total;
+    const int c = __builtin_amdgcn_readfirstlane(wactive ? find_keyframe(pref, n, witem) : 0);
+    const StereoArgs a = tab[c];
+    const int idx = (witem - pref[c]) * GPW + grp;
+    const bool active = wactive && idx < gp(a.scal_ro)->mask_count;
+    if (stereo_pixel<T, TI, PAT, NS>(a, active ? idx : 0, active, lane)) atomicAdd(&upd[c], 1);
   }
   __syncthreads();
   for (int c = threadIdx.x; c < n; c += blockDim.x)
-    if (upd[c]) atomicAdd(&tab[c].scal->n_updated, upd[c]);
+    if (upd[c]) atomicAdd(&gp(tab[c].scal)->n_updated, upd[c]);
 }
 
 // Copies the caller's frame into rows of `st` bytes, zero padded, plus one zero row.
@@ -480,24 +514,22 @@ __global__ void k_stage_frame(const uint8_t* src, uint8_t* dst, int W, int H, in
   }
 }
 
-// Batched staging: every keyframe's frame, plus a reset of its update counter.
-__global__ void k_stage_batch(const StereoArgs* tab, int n) {
-  __shared__ int pref[KF_BATCH_MAX + 1];
-  block_prefix(n, [&](int c) { return (tab[c].H + 1) * tab[c].i1_stride; }, pref);
-  const int total = pref[n];
+// Batched staging: row y of the grid stages active keyframe y's frame (as
+// k_stage_frame does) and resets its update counter.
+__global__ void k_stage_batch(const StereoArgs* __restrict__ tab, const int32_t* __restrict__ n_dev) {
+  if ((int)blockIdx.y >= *n_dev) return;
+  const StereoArgs& a = tab[blockIdx.y];
+  const int st = a.i1_stride, W = a.W, H = a.H;
+  const int total = (H + 1) * st;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
-    const int c = find_keyframe(pref, n, i);
-    const StereoArgs& a = tab[c];
-    const int k = i - pref[c];
-    const int r = k / a.i1_stride, col = k - r * a.i1_stride;
-    a.i1s[k] = (r < a.H && col < a.W) ? a.i1[(size_t)r * a.W + col] : (uint8_t)0;
+    const int r = i / st, col = i - r * st;
+    gp(a.i1s)[i] = (r < H && col < W) ? gp(a.i1)[(size_t)r * W + col] : (uint8_t)0;
   }
-  if (blockIdx.x == 0)
-    for (int c = threadIdx.x; c < n; c += blockDim.x) tab[c].scal->n_updated = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) gp(a.scal)->n_updated = 0;
 }
 
 template <typename T, typename TI, int PAT>
-hipError_t stereo_batch_ns(int ns, const StereoArgs* tab, int n, int blocks, hipStream_t s) {
+hipError_t stereo_batch_ns(int ns, const StereoArgs* tab, const int32_t* n, int blocks, hipStream_t s) {
   switch (ns) {
 #define KF_NS(v) case v: hipLaunchKernelGGL((k_stereo_batch<T, TI, PAT, v>), dim3(blocks), dim3(ST_THREADS), 0, s, tab, n); break;
     KF_NS(4) KF_NS(8) KF_NS(16) KF_NS(32) KF_NS(64) KF_NS(128) KF_NS(256) KF_NS(512) KF_NS(1024)
@@ -508,7 +540,7 @@ hipError_t stereo_batch_ns(int ns, const StereoArgs* tab, int n, int blocks, hip
 }
 
 template <int PREC>
-hipError_t stereo_batch_prec(int pattern, int ns, const StereoArgs* tab, int n, int blocks, hipStream_t s) {
+hipError_t stereo_batch_prec(int pattern, int ns, const StereoArgs* tab, const int32_t* n, int blocks, hipStream_t s) {
   using T = typename Form<PREC>::T;
   using TI = typename Form<PREC>::TI;
   if (pattern == KF_PAT_LINE5) return stereo_batch_ns<T, TI, KF_PAT_LINE5>(ns, tab, n, blocks, s);
@@ -542,9 +574,9 @@ int stereo_grid_blocks(int device) {
   return cus * 8;
 }
 
-hipError_t launch_stereo_batch(int prec, int pattern, int ns, const StereoArgs* tab, int n, int blocks,
-                               hipStream_t s) {
-  hipLaunchKernelGGL(k_stage_batch, dim3(blocks), dim3(256), 0, s, tab, n);
+hipError_t launch_stereo_batch(int prec, int pattern, int ns, const StereoArgs* tab, const int32_t* n, int nmax,
+                               int blocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_stage_batch, dim3(64, nmax), dim3(256), 0, s, tab, n);
   switch (prec) {
     case KF_F64: return stereo_batch_prec<KF_F64>(pattern, ns, tab, n, blocks, s);
     case KF_F32: return stereo_batch_prec<KF_F32>(pattern, ns, tab, n, blocks, s);

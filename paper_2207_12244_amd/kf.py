@@ -109,6 +109,7 @@ def load_library(path: Optional[str] = None):
         "kf_batch_workspace_bytes": (c_size_t, [POINTER(P), c_int32]),
         "kf_batch_create": (c_int32, [POINTER(P), c_int32, POINTER(KfBatchConfig), POINTER(P)]),
         "kf_batch_fuse": (c_int32, [P, POINTER(P), POINTER(c_double)]),
+        "kf_batch_fuse_subset": (c_int32, [P, c_int32, POINTER(c_int32), POINTER(P), POINTER(c_double)]),
         "kf_batch_stereo_update": (c_int32, [P, POINTER(P), POINTER(c_double)]),
         "kf_batch_solve": (c_int32, [P]),
         "kf_batch_layout": (c_int32, [P, POINTER(c_int32)]),
@@ -128,7 +129,7 @@ EXPORTED_SYMBOLS = (
     "kf_set_prior", "kf_stereo_update", "kf_solve", "kf_fuse_frame", "kf_read_depth", "kf_read_stats",
     "kf_export_state", "kf_import_state", "kf_solver_layout",
     "kf_batch_config_default", "kf_batch_workspace_bytes", "kf_batch_create", "kf_batch_fuse",
-    "kf_batch_stereo_update", "kf_batch_solve", "kf_batch_layout",
+    "kf_batch_fuse_subset", "kf_batch_stereo_update", "kf_batch_solve", "kf_batch_layout",
     "kf_batch_last_error", "kf_batch_destroy",
 )
 
@@ -265,6 +266,16 @@ def kf_batch_fuse(batch, images, poses) -> None:
     """images: sequence of device pointers (int or c_void_p); poses: sequence of 4x4 matrices."""
     arr, P = _frame_args(images, poses)
     _bcheck(load_library().kf_batch_fuse(batch, arr, P.ctypes.data_as(POINTER(c_double))), batch)
+
+
+def kf_batch_fuse_subset(batch, members, images, poses) -> None:
+    """members: indices into the batch; images / poses: one per listed member."""
+    if len(members) == 0:
+        return
+    arr, P = _frame_args(images, poses)
+    idx = (c_int32 * len(members))(*[int(i) for i in members])
+    _bcheck(load_library().kf_batch_fuse_subset(batch, len(members), idx, arr,
+                                                P.ctypes.data_as(POINTER(c_double))), batch)
 
 
 def kf_batch_stereo_update(batch, images, poses) -> None:
@@ -450,6 +461,14 @@ class Batch:
 
     def stereo_update(self, images, poses):
         kf_batch_stereo_update(self.batch, self._ptrs(images, poses), poses)
+
+    def fuse_subset(self, members, images, poses):
+        """Fuses images[k] / poses[k] into member members[k]; the others are untouched."""
+        if len(images) != len(members) or len(poses) != len(members):
+            raise ValueError("need one image and pose per listed member")
+        ptrs = [self.members[i]._img(im, f"images[{k}]") for k, (i, im) in enumerate(zip(members, images))]
+        self._keep = list(images)
+        kf_batch_fuse_subset(self.batch, members, ptrs, poses)
 
     def solve(self):
         kf_batch_solve(self.batch)

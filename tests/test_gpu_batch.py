@@ -89,3 +89,25 @@ def test_batch_queues_more_teams_than_resident_workgroups():
     for i, (a, b) in enumerate(zip(solo, members)):
         _assert_same(_state(a), _state(b), f"member {i}")
     batch.close()
+
+
+def test_batch_subset_calls_equal_solo():
+    """kf_batch_fuse_subset: listed members advance exactly as alone; the rest stay untouched."""
+    from paper_2207_12244_amd.kf import Batch
+    t = torch()
+    cases = [kfsynth.config_case(3, 60 + i, size_index=i % 4, frames=3) for i in range(5)]
+    solo = [_make(c) for c in cases]
+    members = [_make(c) for c in cases]
+    batch = Batch(members)
+    plan = [[0, 1, 2, 3, 4], [0, 2, 4], [3, 1]]
+    say(f"batch subset: plan {plan}")
+    for f, active in enumerate(plan):
+        imgs = [dev(cases[i].images[f], t.uint8) for i in active]
+        poses = [cases[i].poses[f] for i in active]
+        for k, i in enumerate(active):
+            solo[i].fuse_frame(imgs[k], poses[k])
+        batch.fuse_subset(active, imgs, poses)
+    t.cuda.synchronize()
+    for i in range(len(cases)):
+        _assert_same(_state(solo[i]), _state(members[i]), f"member {i}")
+    batch.close()
