@@ -42,6 +42,8 @@ SOLVER_SRC = os.path.join(ROOT, "paper_2207_12244_amd", "csrc", "kf_solve.hip")
 WORKLOAD = dict(config=2, W=640, H=480, frames=30, precision="bf16", pattern="sq5x5", n_samples=128,
                 n_gn=10, n_cg=20)
 BATCHED = dict(config=3, keyframes=64, precision="bf16", pattern="line5", n_samples=32, n_gn=10, n_cg=20)
+SERVING = dict(config=4, streams=32, requests=40, keyframe_every=20, views=4, precision="f32", pattern="sq5x5",
+               n_samples=64, n_gn=10, n_cg=20, budget_gib=64)
 
 
 def solver_bytes_per_frame(N, n_gn, n_cg, word=4):
@@ -212,6 +214,76 @@ def kfsynth_seed(config, case):
     return kfsynth.seed_for(config, case)
 
 
+def _gen_serving_stream(i):
+    from kfsynth.serving import serving_stream
+    w = SERVING
+    return serving_stream(i, w["requests"], views=w["views"], keyframe_every=w["keyframe_every"])
+
+
+def serving_streams(n):
+    """The serving workload's request streams, generated in a process pool."""
+    import concurrent.futures
+    import multiprocessing
+    t_gen = time.perf_counter()
+    workers = max(1, min(8, os.cpu_count() or 1))
+    ctx = multiprocessing.get_context("fork")
+    with concurrent.futures.ProcessPoolExecutor(workers, mp_context=ctx) as ex:
+        out = list(ex.map(_gen_serving_stream, range(n)))
+    print(f"# serving: generated {len(out)} streams in {time.perf_counter() - t_gen:.1f}s", file=sys.stderr, flush=True)
+    return out
+
+
+def run_serving(a, torch, streams):
+    """Serving form: 32 camera streams with Poisson arrivals at 30 Hz each."""
+    from paper_2207_12244_amd import autotune
+    from paper_2207_12244_amd.serve import Request, Server
+    w = SERVING
+    sizes = [(c.W, c.H) for c, _ in streams]
+    pol = autotune.tuned_policy(sizes, w["precision"], w["n_gn"], w["n_cg"]) if a.serving_tiles == "tuned" else None
+    srv = Server(w["budget_gib"] << 30, precision=w["precision"], pattern=w["pattern"], n_samples=w["n_samples"],
+                 n_gn=w["n_gn"], n_cg=w["n_cg"], solver_threads=pol["threads"] if pol else 512,
+                 px_per_thread=pol["ppt"] if pol else None)
+    for c, _ in streams:
+        srv.open_stream(c.W, c.H, c.K)
+    srv.start()
+
+    def submit_all(offset):
+        for sid, (c, reqs) in enumerate(streams):
+            for r in reqs:
+                srv.submit(sid, Request(r["kind"], r["t"] + offset, r["image"], r["pose"], r.get("priors")))
+
+    # warm-up pass over the same requests (graphs, clocks), then the measured pass
+    submit_all(1.0)
+    srv.run()
+    submit_all(1.0)
+    st = srv.run()
+    # capacity: the same requests arriving 20x faster (600 Hz per stream), far beyond what the device sustains
+    for sid, (c, reqs) in enumerate(streams):
+        for r in reqs:
+            srv.submit(sid, Request(r["kind"], r["t"] / 20.0, r["image"], r["pose"], r.get("priors")))
+    cap = srv.run()
+    hist = {}
+    for W, H in sizes:
+        hist[f"{W}x{H}"] = hist.get(f"{W}x{H}", 0) + 1
+    out = {"value": round(st["mpx_s"], 3), "unit": "Mpixel/s",
+           "latency_ms": {k: round(v, 4) for k, v in st["latency_ms"].items()},
+           "frames": st["frames"], "seconds": round(st["seconds"], 3), "calls": st["calls"],
+           "mean_streams_per_call": round(st["mean_streams_per_call"], 2),
+           "capacity": {"mpx_s": round(cap["mpx_s"], 3), "arrivals": "same requests at 20x the rate",
+                        "latency_ms": {k: round(v, 4) for k, v in cap["latency_ms"].items()},
+                        "mean_streams_per_call": round(cap["mean_streams_per_call"], 2)},
+           "config": {"workload": f"{len(streams)} camera streams, Poisson arrivals at 30 Hz each, a new keyframe "
+                                  f"every {w['keyframe_every']} requests, f32 maps, SQ5X5, N_s={w['n_samples']}, "
+                                  f"{w['n_gn']} GN x {w['n_cg']} PCG; latency = completion - arrival incl. the "
+                                  "host-to-device copy of the frame",
+                      "sizes": hist, "requests_per_stream": w["requests"],
+                      "hbm_budget_bytes": srv.budget, "hbm_admitted_bytes": srv.used,
+                      "shape_policy": {"threads": pol["threads"], "px_per_thread_cap": pol["ppt"]} if pol
+                      else "latency-optimal per size"}}
+    srv.close()
+    return out
+
+
 def run_headline(a, torch):
     """The headline workload: one 640 x 480 keyframe fused with a 30-frame sequence."""
     import kfsynth
@@ -327,8 +399,11 @@ def main(argv=None):
     ap.add_argument("--solver-threads", type=int, default=0, help="solver workgroup size (0 = automatic)")
     ap.add_argument("--cooperative", action="store_true", help="launch the solver cooperatively")
     ap.add_argument("--cg-variant", default="auto", choices=["auto", "textbook", "pipelined"])
-    ap.add_argument("--form", default="all", choices=["all", "headline", "batched"],
-                    help="headline 640x480 sequence, the batched form, or both (batched under \"batched\")")
+    ap.add_argument("--form", default="all", choices=["all", "headline", "batched", "serving"],
+                    help="headline 640x480 sequence, the batched or serving form, or all three "
+                         "(batched and serving under their own keys)")
+    ap.add_argument("--serving-tiles", default="auto", choices=["tuned", "auto"],
+                    help="serving tile shapes: latency-optimal per size (auto) or the batch autotuner's")
     ap.add_argument("--batched-steps", type=int, default=10)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 256 MiB device-to-device copy (HBM counter calibration)")
@@ -339,8 +414,9 @@ def main(argv=None):
               file=sys.stderr)
         return 2
 
-    # the batched workload is generated in a process pool before the GPU is touched
+    # the batched and serving workloads are generated in process pools before the GPU is touched
     batched_in = batched_cases(BATCHED["keyframes"]) if a.form in ("all", "batched") else None
+    serving_in = serving_streams(SERVING["streams"]) if a.form in ("all", "serving") else None
 
     import torch
     if not torch.cuda.is_available():
@@ -351,10 +427,16 @@ def main(argv=None):
         out = {"metric": "batched keyframe-update Mpixel/s (64 mixed-size keyframes)", **out, "n_gpus": 1,
                "warmup": a.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
                "data": "synthetic"}
+    elif a.form == "serving":
+        out = run_serving(a, torch, serving_in)
+        out = {"metric": "served keyframe-update Mpixel/s + p50/p99 latency (32 streams)", **out, "n_gpus": 1,
+               "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic"}
     else:
         out = run_headline(a, torch)
         if batched_in is not None:
             out["batched"] = run_batched(a, torch, batched_in)
+        if serving_in is not None:
+            out["serving"] = run_serving(a, torch, serving_in)
     print(json.dumps(out), flush=True)
     return 0
 
