@@ -63,8 +63,11 @@ def _load(path: str) -> dict:
 
 
 def _device_name() -> str:
+    """Architecture and compute-unit count of device 0, e.g. "gfx950-256cu"."""
     import torch
-    return torch.cuda.get_device_properties(0).name.replace("|", "/")
+    p = torch.cuda.get_device_properties(0)
+    arch = getattr(p, "gcnArchName", "") or p.name
+    return f"{arch.split(':')[0]}-{p.multi_processor_count}cu".replace("|", "/")
 
 
 def measure_policy(sizes: Sequence[Tuple[int, int]], threads: int, ppt: int, precision: str = "bf16",
