@@ -54,8 +54,15 @@ def solver_bytes_per_frame(N, n_gn, n_cg, word=4):
 
 
 def source_hash(path):
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """sha256 (16 hex) of a source file's code with comments and blank space
+    removed, so that comment edits do not invalidate counters of an unchanged kernel."""
+    import re
+    with open(path) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    text = "\n".join(line.strip() for line in text.splitlines() if line.strip())
+    return hashlib.sha256(text.encode()).hexdigest()[:16]
 
 
 def load_traffic(path=TRAFFIC_FILE):

@@ -1,23 +1,26 @@
 // Optimisation (Sec. II-C): n_gn Gauss-Newton iterations alternating between the
 // log-depth map x and the scale tau = ln s, each depth step solved by Jacobi-
-// preconditioned CG on the 5-point normal equations, all in ONE persistent,
-// cooperatively launched kernel.
+// preconditioned CG on the 5-point normal equations, all in ONE persistent
+// launch per frame (per batch of keyframes in the batched form).
 //
-// Decomposition: the keyframe is cut into tiles_x x tiles_y tiles; workgroup b
-// owns tile b for the whole launch and keeps its CG vectors in registers and a
-// one-pixel ghost ring of the stencil operand in LDS. Workgroups never meet at
-// a grid barrier. At each synchronisation point every workgroup publishes its
-// partial sums and its tile boundary as 64-bit words tagged with an epoch
-// number (relaxed agent-scope atomic stores), then polls the words it needs:
-// all partials of the team (summed in a fixed order, so every workgroup gets
-// bit-identical totals) and the boundaries of its four neighbours. Slots are
-// double-buffered by epoch parity; no workgroup can run two synchronisations
-// ahead of another because each one waits for every partial.
+// Decomposition: the keyframe is cut into tiles_x x tiles_y tiles; a team of
+// workgroups, member b owning tile b, keeps the CG vectors of its pixels in
+// registers and a one-pixel ghost ring of the stencil operand in LDS for the
+// whole solve. Workgroups never meet at a grid barrier. At each
+// synchronisation point every member publishes its partial sums and its tile
+// boundary as 64-bit words tagged with an epoch number (relaxed agent-scope
+// atomic stores), then polls the words it needs: all partials of the team
+// (summed in a fixed order, so every member gets bit-identical totals) and the
+// boundaries of its four neighbours. Slots are double-buffered by epoch
+// parity; no member can run two synchronisations ahead of another because each
+// one waits for every partial.
 //
-// Per GN iteration: 1 synchronisation for the initial residual, 2 per PCG
-// iteration (p.q; then r.z with the z boundary from which every workgroup
-// rebuilds its ghost copy of p), minus the last r.z in fixed-count mode, and 1
-// for the scale step (which also ships the x boundary).
+// Per GN iteration: 1 synchronisation for the initial residual, then per PCG
+// iteration 1 (pipelined variant: both inner products and the boundary of the
+// next stencil operand) or 2 (textbook variant: p.q; then r.z with the z
+// boundary from which every member rebuilds its ghost copy of p, the last r.z
+// skipped in fixed-count mode), and 1 for the scale step (which also ships the
+// x boundary).
 #include "kf_internal.h"
 
 namespace kf {
