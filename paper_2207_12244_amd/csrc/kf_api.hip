@@ -146,7 +146,7 @@ bool layout_for(const kf_config& c, const Tiling& t, Layout* L) {
   L->match = off; off += align256(N * 4);
   L->i1s = off; off += align256((size_t)(c.height + 1) * stage_stride(c.width));
   L->scal = off; off += 256;
-  L->parts = off; off += align256((size_t)2 * NV_MAX * t.blocks * 2 * 8);
+  L->parts = off; off += align256((size_t)2 * NV_MAX * PART_REPLICAS * t.blocks * 2 * 8);
   L->halo = off; off += align256((size_t)2 * t.blocks * (2 * t.tile_w + 2 * t.tile_h) * 2 * 8);
   L->total = off;
   return true;

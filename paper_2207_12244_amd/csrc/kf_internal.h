@@ -108,6 +108,7 @@ struct Tiling {
 };
 
 constexpr int NV_MAX = 3;            // values reduced per synchronisation
+constexpr int PART_REPLICAS = 4;     // copies of each published partial (readers spread over them)
 constexpr int MAX_TEAM = 256;        // workgroups per keyframe team
 constexpr int CHUNK = 256;           // pixels per compaction chunk
 #define KF_BATCH_MAX KF_BATCH_MAX_MEMBERS
@@ -163,7 +164,7 @@ struct SolveArgs {
   const void* rho; const void* var;
   void* x;
   DevScalars* scal;
-  uint64_t* parts;           // [2][NV_MAX][blocks][2] exchange words
+  uint64_t* parts;           // [2][NV_MAX][PART_REPLICAS][blocks][2] exchange words
   uint64_t* halo;            // [2][blocks][perim][2]
   int perim;                 // 2 tile_w + 2 tile_h
   uint32_t epoch_span;       // epochs one launch may use (the base lives in DevScalars::epoch)

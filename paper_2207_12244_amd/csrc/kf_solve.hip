@@ -134,8 +134,11 @@ struct Team {
   int g_off[GMAX];  // offset in its boundary list
   int g_li[GMAX];   // ring index
 
-  __device__ KF_GLOBAL uint64_t* part_slot(uint32_t e, int v, int j) const {
-    return parts + ((size_t)((e & 1u) * NV_MAX + v) * B + j) * 2;
+  // Replica r of member j's partial v: every member writes all replicas and
+  // reads replica (own index mod PART_REPLICAS), so the team's polling loads
+  // spread over several copies of the hot words.
+  __device__ KF_GLOBAL uint64_t* part_slot(uint32_t e, int v, int j, int r) const {
+    return parts + ((size_t)(((e & 1u) * NV_MAX + v) * PART_REPLICAS + r) * B + j) * 2;
   }
   __device__ KF_GLOBAL uint64_t* halo_slot(uint32_t e, int blk, int off) const {
     return halo + ((size_t)((e & 1u) * B + blk) * perim + off) * 2;
@@ -155,7 +158,17 @@ struct Team {
   // all workgroups hold bit-identical totals. All words a thread waits for are
   // loaded together each polling round. Returns false if the team aborts.
   __device__ bool sync(uint32_t e, int nv, const double* vals, double* tot, T* gval, bool ghosts, T* ring = nullptr) {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    return sync(e, nv, vals, tot, gval, ghosts, ring, [] {});
+  }
+
+  // As above; `pre()` runs in every thread after the workgroup has published
+  // its partials and before it polls: work that needs no neighbour data (and
+  // may read LDS written before the synchronisation) overlaps the wait.
+  template <typename F>
+  __device__ bool sync(uint32_t e, int nv, const double* vals, double* tot, T* gval, bool ghosts, T* ring, F&& pre) {
+    int tid = threadIdx.x;
+    refresh(tid);
+    const int lane = tid & 63, wave = tid >> 6;
 #pragma unroll
     for (int m = 0; m < GMAX; ++m) {
       refresh(g_src[m]);
@@ -167,12 +180,14 @@ struct Team {
       if (lane == 0) s_wred[wave * NV_MAX + v] = s;
     }
     __syncthreads();
-    if (tid < nv) {
+    if (tid < nv * PART_REPLICAS) {
+      const int v = tid % nv, r = tid / nv;
       double p = 0.0;
-      for (int w = 0; w < NW; ++w) p += s_wred[w * NV_MAX + tid];
-      if (packed) st_word(part_slot(e, tid, b), Packed48::make_word(p, e));
-      else Wire<double>::put(part_slot(e, tid, b), p, e);
+      for (int w = 0; w < NW; ++w) p += s_wred[w * NV_MAX + v];
+      if (packed) st_word(part_slot(e, v, b, r), Packed48::make_word(p, e));
+      else Wire<double>::put(part_slot(e, v, b, r), p, e);
     }
+    pre();
     // poll set of this thread
     const int nslots = nv * B;
     bool p_ready[PSLOTS], g_ready[GMAX];
@@ -190,7 +205,7 @@ struct Team {
       for (int q = 0; q < PSLOTS; ++q) {
         if (!p_ready[q]) {
           const int s = tid + q * NT, v = s / B, j = s - v * B;
-          const KF_GLOBAL uint64_t* w = part_slot(e, v, j);
+          const KF_GLOBAL uint64_t* w = part_slot(e, v, j, b % PART_REPLICAS);
           pw0[q] = ld_word(w);
           if (!packed) pw1[q] = ld_word(w + 1);
         }
@@ -498,8 +513,26 @@ __device__ __forceinline__ void solve_member(const SolveArgs& a, const int b, un
           tm.publish(e, KF_LX(j), KF_LY(j), mv[j]);
         }
         vals[0] = ga; vals[1] = de;
+        // the stencil product of the tile's interior pixels needs no ghost
+        // value: it is formed while the team's words are in flight (for up to
+        // 4 pixels per thread; with more, the extra registers cost more than
+        // the overlap gains)
+        constexpr bool OVERLAP = PPT <= 4;
+        T nint[PPT];
+        auto interior = [&] {
+#pragma unroll
+          for (int j = 0; j < PPT; ++j) {
+            nint[j] = (T)0;
+            if (!OVERLAP || lxy[j] < 0) continue;
+            const int lx = KF_LX(j), ly = KF_LY(j);
+            if (lx == 0 || ly == 0 || lx == tw - 1 || ly == th - 1) continue;
+            const int l = KF_LI(j);
+            nint[j] = dg[j] * mv[j] - cR[j] * mring[l + 1] - cL[j] * mring[l - 1] - cD[j] * mring[l + rw] -
+                      cU[j] * mring[l - rw];
+          }
+        };
         // the neighbours' m lands directly in the ghost ring of mring
-        if (!tm.sync(e++, 2, vals, tot, gval, true, mring)) return;
+        if (!tm.sync(e++, 2, vals, tot, gval, true, mring, interior)) return;
         if (tot[0] == 0.0) break;
         double beta = 0.0, alpha;
         if (i > 0) {
@@ -519,8 +552,11 @@ __device__ __forceinline__ void solve_member(const SolveArgs& a, const int b, un
           xr[j] = fma(al, pv[j], xr[j]);
           if (last) continue;
           const int l = KF_LI(j);
-          const T n = dg[j] * mv[j] - cR[j] * mring[l + 1] - cL[j] * mring[l - 1] - cD[j] * mring[l + rw] -
-                      cU[j] * mring[l - rw];
+          const int lx = KF_LX(j), ly = KF_LY(j);
+          T n = nint[j];
+          if (!OVERLAP || lx == 0 || ly == 0 || lx == tw - 1 || ly == th - 1)
+            n = dg[j] * mv[j] - cR[j] * mring[l + 1] - cL[j] * mring[l - 1] - cD[j] * mring[l + rw] -
+                cU[j] * mring[l - rw];
           zv[j] = i > 0 ? fma(be, zv[j], n) : n;
           qv[j] = i > 0 ? fma(be, qv[j], mv[j]) : mv[j];
           sv[j] = i > 0 ? fma(be, sv[j], wv[j]) : wv[j];
