@@ -92,7 +92,23 @@ def cpu_baseline(case, wl):
     cores = max(1, int(round((c1 - c0) / wall)))
     return {"value": round(case.W * case.H / wall / 1e6, 6), "unit": "Mpixel/s", "cores": cores, "kind": "oracle",
             "sample": f"1 frame (frame 1 of the 30-frame sequence) of the same {case.W}x{case.H} workload, "
-                      f"{wall:.1f} s wall on the host", "seconds": round(wall, 3)}
+                      f"{wall:.1f} s wall on the host", "seconds": round(wall, 3)}, ok
+
+
+def accuracy_vs_oracle(ok, case, wl, torch):
+    """Depth of the GPU form after the same first frame, against the oracle's."""
+    from paper_2207_12244_amd.kf import Keyframe
+    dev = lambda x, dt: torch.as_tensor(np.ascontiguousarray(x), dtype=dt, device="cuda")
+    kf = Keyframe(case.W, case.H, precision=wl["precision"], pattern=wl["pattern"], n_samples=wl["n_samples"],
+                  n_gn=wl["n_gn"], n_cg=wl["n_cg"], K=case.K)
+    kf.set_prior(dev(case.image0, torch.uint8), *[dev(m, torch.float32) for m in case.priors.maps()], case.T_wc0)
+    kf.fuse_frame(dev(case.images[0], torch.uint8), case.poses[0])
+    d, s = kf.read_depth()
+    d_o, s_o = ok.read_depth()
+    rel = np.abs(d.cpu().numpy().astype(np.float64) / d_o - 1.0)
+    return {"depth_rel_err_max": float(f"{rel.max():.4g}"), "depth_rel_err_rms": float(f"{np.sqrt(np.mean(rel ** 2)):.4g}"),
+            "scale_rel_err": float(f"{abs(s / s_o - 1.0):.4g}"),
+            "against": "FP64 oracle, same first frame, iteration-matched 10 x 20 Jacobi PCG"}
 
 
 def _gen_batched_case(i):
@@ -385,7 +401,8 @@ def run_headline(a, torch):
                              "resolution unstated (Table IV)"},
     }
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(case, wl)
+        out["cpu_baseline"], ok = cpu_baseline(case, wl)
+        out["accuracy"] = accuracy_vs_oracle(ok, case, wl, torch)
     return out
 
 

@@ -23,7 +23,7 @@ import time
 from typing import Iterable, Optional, Sequence, Tuple
 
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_shapes.json")
-CANDIDATES = ((512, 10), (512, 8), (512, 6), (1024, 3), (512, 3))
+CANDIDATES = ((512, 10), (512, 8), (512, 6), (1024, 3), (512, 4), (512, 3))
 MAX_TEAM = 256
 
 

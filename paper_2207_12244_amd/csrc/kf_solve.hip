@@ -680,9 +680,12 @@ __global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
 // Batched form: workgroup g works through its queue of (keyframe, member)
 // entries in order. Queues list teams in one global order, so the lowest
 // unfinished team always has every member at it and the launch cannot
-// deadlock, provided all workgroups are co-resident.
+// deadlock, provided all workgroups are co-resident. 512-thread workgroups of
+// up to 4 pixels per thread are held to 128 registers so that two of them
+// share a compute unit (one computes while the other's team synchronises).
 template <typename T, int NT, int PPT, bool PIPE>
-__global__ __launch_bounds__(NT) void k_solve_batch(const SolveArgs* __restrict__ tab,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 512 && NT * PPT <= 2048 ? 4 : 1)))
+void k_solve_batch(const SolveArgs* __restrict__ tab,
                                                     const int32_t* __restrict__ queue,
                                                     const int32_t* __restrict__ qoff) {
   extern __shared__ __align__(16) unsigned char smem[];
