@@ -60,3 +60,40 @@ def test_admission_refuses_over_budget():
     with pytest.raises(AdmissionError):
         srv3.open_stream(640, 480, K)
     srv2.close()
+
+
+def test_streams_admitted_as_memory_frees():
+    """Three streams requested under a budget that holds two at a time: the
+    third is admitted once an earlier one has finished and released its
+    memory, and every stream's result equals the stream served alone."""
+    from paper_2207_12244_amd.kf import Keyframe
+    from paper_2207_12244_amd.serve import Request, Server
+    from kfsynth.serving import serving_stream
+    t = torch()
+    streams = [serving_stream(i, 8, views=3, keyframe_every=20, rate_hz=200.0) for i in range(3)]
+    probe = Server(1 << 40, **KW)
+    needs = [probe.stream_bytes(c.W, c.H) for c, _ in streams]
+    budget = sorted(needs)[-1] + sorted(needs)[-2] + (1 << 20)     # any two streams plus the batch tables
+    srv = Server(budget, keep_results=True, **KW)
+    sids = [srv.request_stream(c.W, c.H, c.K, [Request(r["kind"], r["t"], r["image"], r["pose"], r.get("priors"))
+                                               for r in reqs]) for c, reqs in streams]
+    stats = srv.run()
+    say(f"admissions {srv.admissions} closes {srv.closes} stats {stats}")
+    assert stats["frames"] == sum(sum(1 for r in reqs if r["kind"] == "frame") for _, reqs in streams)
+    admitted_at = dict(srv.admissions)
+    closed_at = dict(srv.closes)
+    assert max(admitted_at.values()) >= min(closed_at.values())      # the last one waited for a close
+    assert srv.used <= budget
+    # replay each stream alone and compare with what the served stream ended with
+    for (c, reqs), sid in zip(streams, sids):
+        alone = Keyframe(c.W, c.H, K=c.K, solver_threads=512, **KW)
+        for r in reqs:
+            if r["kind"] == "keyframe":
+                alone.set_prior(dev(r["image"], t.uint8), *[dev(m, t.float32) for m in r["priors"]], r["pose"])
+            else:
+                alone.fuse_frame(dev(r["image"], t.uint8), r["pose"])
+        a, b = alone.export_state(), srv.results[sid]
+        for k in ("x", "rho", "var", "match"):
+            assert np.array_equal(a[k].cpu().numpy(), b[k].cpu().numpy()), (sid, k)
+        assert a["tau"] == b["tau"]
+    srv.close()
