@@ -65,15 +65,18 @@ def source_hash(path):
     return hashlib.sha256(text.encode()).hexdigest()[:16]
 
 
-def load_traffic(path=TRAFFIC_FILE):
+def load_traffic(path=TRAFFIC_FILE, layout=None):
     """HBM bytes per solver launch from a committed rocprofv3 counter summary,
-    or None when the solver source changed since the counters were taken."""
+    or None when the solver source or the launch layout changed since the
+    counters were taken."""
     try:
         with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
     if t.get("kf_solve_hip_sha256_16") != source_hash(SOLVER_SRC):
+        return None
+    if layout is not None and t.get("launch_layout") != layout:
         return None
     return t.get("hbm_bytes_per_launch")
 
@@ -223,7 +226,7 @@ def run_batched(a, torch, cases):
                               "solve": round(float(np.mean(solve_ms)), 4)},
         "roofline": {"kernel": "k_solve_batch", "bound": "hbm", "achieved": round(achieved, 2),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": load_traffic(BATCH_TRAFFIC_FILE), "algorithmic_bytes_per_launch": bpl,
+                     "traffic": load_traffic(BATCH_TRAFFIC_FILE, batch.layout()), "algorithmic_bytes_per_launch": bpl,
                      "avg_launch_ms": round(solve_avg_s * 1000.0, 4)},
     }
     if not a.no_cpu_baseline:
@@ -365,7 +368,7 @@ def run_headline(a, torch):
     bpl = solver_bytes_per_frame(N, wl["n_gn"], wl["n_cg"])
     solve_avg_s = float(np.mean(solve_ms)) / 1000.0
     achieved = bpl / solve_avg_s / 1e9
-    traffic = load_traffic()
+    traffic = load_traffic(TRAFFIC_FILE, kf.solver_layout())
     out = {
         "metric": METRIC,
         "value": round(value, 3),

@@ -84,13 +84,13 @@ bool tiling_ok(int W, int H, int tx, int ty, int threads, int prec, Tiling* t) {
 }  // namespace
 
 // Latency model of one PCG iteration of a team (microseconds), fitted to
-// MI355X measurements of the 640 x 480 solve: a synchronisation costs ~2.1 us
-// plus 6.5 ns per workgroup polled, and a workgroup spends ~0.85 ns per tile
-// pixel at 512 threads (0.95 at 1024, 1.65 at 256, whose single wavefront per
+// MI355X measurements of the 640 x 480 solve (200-256 workgroups): ~1.27 us
+// per synchronisation plus 4 ns per workgroup polled, and ~1.25 ns per tile
+// pixel at 512 threads (1.45 at 1024, 2.4 at 256, whose single wavefront per
 // SIMD hides little latency), with a small penalty for long tile perimeters.
 double iteration_us(const Tiling& c) {
-  const double per_px = c.threads == 256 ? 1.65e-3 : (c.threads == 512 ? 0.85e-3 : 0.95e-3);
-  return 2.1 + 0.0065 * c.blocks + (double)c.tile_w * c.tile_h * per_px + (c.tile_w + c.tile_h) * 1e-4;
+  const double per_px = c.threads == 256 ? 2.4e-3 : (c.threads == 512 ? 1.25e-3 : 1.45e-3);
+  return 1.27 + 0.004 * c.blocks + (double)c.tile_w * c.tile_h * per_px + (c.tile_w + c.tile_h) * 1e-4;
 }
 
 // Picks the tile grid (and workgroup size, unless given) minimising iteration_us.
