@@ -96,6 +96,9 @@ typedef struct {
   int32_t solver_threads;       /* threads per solver workgroup: 0 = automatic, 256, 512 or 1024 */
   int32_t solver_cooperative;   /* 1: hipLaunchCooperativeKernel; 0: plain launch whose grid is
                                    checked against the device's co-resident capacity */
+  double solver_timeout_ms;     /* longest a solver workgroup waits for its team before the whole
+                                   team gives up and flags KF_ERR_TIMEOUT (0 = default 2000 ms).
+                                   After a timeout the state is undefined: call kf_set_prior. */
   void* stream;                 /* hipStream_t the context enqueues on (NULL = null stream) */
   void* workspace;              /* device buffer of at least kf_workspace_bytes(cfg) bytes */
   size_t workspace_bytes;

@@ -46,6 +46,8 @@ const char* validate(const kf_config& c) {
   if (c.solver_cooperative != 0 && c.solver_cooperative != 1) return "solver_cooperative must be 0 or 1";
   if (c.cg_variant < 0 || c.cg_variant > 2) return "cg_variant must be 0, 1 or 2";
   if (c.cg_variant == 2 && c.cg_rtol > 0.0) return "the pipelined CG variant runs a fixed iteration count (cg_rtol = 0)";
+  if (!(c.solver_timeout_ms >= 0.0) || !std::isfinite(c.solver_timeout_ms) || c.solver_timeout_ms > 3.6e6)
+    return "solver_timeout_ms must be in [0, 3.6e6]";
   return nullptr;
 }
 
@@ -404,7 +406,8 @@ kf_status kf_create(const kf_config* cfg, kf_ctx** out) {
   int rate_khz = 100000;
   if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, c->device) != hipSuccess || rate_khz <= 0)
     rate_khz = 100000;
-  c->timeout_ticks = (uint64_t)rate_khz * 1000ull * 2ull;   // 2 s
+  const double timeout_ms = cfg->solver_timeout_ms > 0.0 ? cfg->solver_timeout_ms : 2000.0;
+  c->timeout_ticks = (uint64_t)((double)rate_khz * timeout_ms);   // wall-clock ticks
   c->stereo_blocks = stereo_grid_blocks(c->device);
   c->coresident = -1;
   *out = c;

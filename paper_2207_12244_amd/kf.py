@@ -48,7 +48,7 @@ class KfConfig(ctypes.Structure):
         ("grad_gate", c_double), ("sigma_photo", c_double), ("r_floor", c_double),
         ("precision", c_int32),
         ("solver_tiles_x", c_int32), ("solver_tiles_y", c_int32),
-        ("solver_threads", c_int32), ("solver_cooperative", c_int32),
+        ("solver_threads", c_int32), ("solver_cooperative", c_int32), ("solver_timeout_ms", c_double),
         ("stream", c_void_p), ("workspace", c_void_p), ("workspace_bytes", c_size_t),
     ]
 
@@ -315,7 +315,7 @@ class Keyframe:
                  n_samples: int = 32, n_gn: int = 10, n_cg: int = 20, cg_rtol: float = 0.0, cg_max: int = 4000,
                  huber_delta: float = 1.345, d_near: float = 0.4, d_far: float = 10.0, grad_gate: float = 6.0,
                  sigma_photo: float = 1.0, r_floor: float = 1e-6, K=None, tiles=(0, 0), solver_threads: int = 0,
-                 cooperative: bool = False, cg_variant: str = "auto", stream=None):
+                 cooperative: bool = False, cg_variant: str = "auto", solver_timeout_ms: float = 0.0, stream=None):
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("Keyframe needs a GPU (the library has no CPU path)")
@@ -332,6 +332,7 @@ class Keyframe:
         cfg.solver_tiles_x, cfg.solver_tiles_y = int(tiles[0]), int(tiles[1])
         cfg.solver_threads, cfg.solver_cooperative = int(solver_threads), int(bool(cooperative))
         cfg.cg_variant = {"auto": 0, "textbook": 1, "pipelined": 2}[cg_variant]
+        cfg.solver_timeout_ms = float(solver_timeout_ms)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         cfg.stream = c_void_p(self.stream.cuda_stream)
         nbytes = kf_workspace_bytes(cfg)

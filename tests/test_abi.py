@@ -46,7 +46,8 @@ def test_defaults_follow_the_documented_readings():
 @pytest.mark.parametrize("field,value", [
     ("width", 4), ("height", 9000), ("n_samples", 48), ("n_samples", 2048), ("pattern", 7), ("n_gn", 0),
     ("n_cg", 0), ("cg_rtol", -1.0), ("huber_delta", 0.0), ("d_near", 20.0), ("sigma_photo", 0.0),
-    ("r_floor", 0.0), ("precision", 9), ("fx", float("nan")),
+    ("r_floor", 0.0), ("precision", 9), ("fx", float("nan")), ("solver_timeout_ms", -1.0),
+    ("solver_timeout_ms", float("inf")), ("solver_threads", 384),
 ])
 def test_invalid_config_rejected(field, value):
     kf, lib = _lib()
@@ -116,7 +117,7 @@ def test_binding_keyword_surface():
     params = inspect.signature(Keyframe.__init__).parameters
     for name in ("precision", "pattern", "n_samples", "n_gn", "n_cg", "cg_rtol", "cg_max", "huber_delta",
                  "d_near", "d_far", "grad_gate", "sigma_photo", "r_floor", "K", "tiles", "solver_threads",
-                 "cooperative", "cg_variant", "stream"):
+                 "cooperative", "cg_variant", "solver_timeout_ms", "stream"):
         assert name in params, name
     import ast
     import os as _os
