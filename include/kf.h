@@ -96,6 +96,10 @@ typedef struct {
   int32_t solver_threads;       /* threads per solver workgroup: 0 = automatic, 256, 512 or 1024 */
   int32_t solver_cooperative;   /* 1: hipLaunchCooperativeKernel; 0: plain launch whose grid is
                                    checked against the device's co-resident capacity */
+  int32_t pipeline_frames;      /* 1: the solve runs on a second, internal stream and the filter state
+                                   is double-buffered, so the next frame's stereo update overlaps the
+                                   current frame's solve (same results); 0: one stream. A context with
+                                   1 cannot join a batch. */
   double solver_timeout_ms;     /* longest a solver workgroup waits for its team before the whole
                                    team gives up and flags KF_ERR_TIMEOUT (0 = default 2000 ms).
                                    After a timeout the state is undefined: call kf_set_prior. */
@@ -163,6 +167,10 @@ kf_status kf_read_depth(kf_ctx* ctx, void* depth_out, void* var_out, double* sca
 /* Statistics of the last stereo update and solve (host struct). Synchronises. */
 kf_status kf_read_stats(kf_ctx* ctx, kf_frame_stats* out);
 
+/* The internal stream the solves run on when cfg.pipeline_frames = 1 (NULL
+   otherwise), for callers that time or order work against the solve. */
+void* kf_solve_stream(const kf_ctx* ctx);
+
 /* Solver decomposition chosen for ctx: tiles_x, tiles_y, tile_w, tile_h, threads. */
 kf_status kf_solver_layout(const kf_ctx* ctx, int32_t out[5]);
 
@@ -206,8 +214,8 @@ size_t kf_batch_workspace_bytes(kf_ctx* const* members, int32_t n);
 
 /* Binds n distinct contexts (1 <= n <= KF_BATCH_MAX_MEMBERS). Members must share
    precision, pattern, n_samples, the solver workgroup size and CG variant, the
-   device and cfg->stream; they may differ in size, intrinsics, tiling and
-   iteration counts. Schedules the solver teams, uploads the static tables and
+   device and cfg->stream, and run without pipeline_frames; they may differ in
+   size, intrinsics, tiling and iteration counts. Schedules the solver teams, uploads the static tables and
    (use_graph) captures the graph; allocates two small pinned host buffers.
    KF_ERR_ARG if the members are incompatible or a team cannot be co-resident.
    Members must outlive the batch; they stay usable on their own between

@@ -44,6 +44,7 @@ const char* validate(const kf_config& c) {
   if (c.solver_threads != 0 && c.solver_threads != 256 && c.solver_threads != 512 && c.solver_threads != 1024)
     return "solver_threads must be 0, 256, 512 or 1024";
   if (c.solver_cooperative != 0 && c.solver_cooperative != 1) return "solver_cooperative must be 0 or 1";
+  if (c.pipeline_frames != 0 && c.pipeline_frames != 1) return "pipeline_frames must be 0 or 1";
   if (c.cg_variant < 0 || c.cg_variant > 2) return "cg_variant must be 0, 1 or 2";
   if (c.cg_variant == 2 && c.cg_rtol > 0.0) return "the pipelined CG variant runs a fixed iteration count (cg_rtol = 0)";
   if (!(c.solver_timeout_ms >= 0.0) || !std::isfinite(c.solver_timeout_ms) || c.solver_timeout_ms > 3.6e6)
@@ -145,6 +146,9 @@ bool layout_for(const kf_config& c, const Tiling& t, Layout* L) {
   L->x = off; off += align256(N * elt);
   L->rho = off; off += align256(N * elt);
   L->var = off; off += align256(N * elt);
+  // second filter-state buffer for frame pipelining (adjacent, cleared together)
+  L->rho2 = off; off += c.pipeline_frames ? align256(N * elt) : 0;
+  L->var2 = off; off += c.pipeline_frames ? align256(N * elt) : 0;
   L->match = off; off += align256(N * 4);
   L->i1s = off; off += align256((size_t)(c.height + 1) * stage_stride(c.width));
   L->scal = off; off += 256;
@@ -173,6 +177,17 @@ template <typename P>
 P* ws_ptr(kf_ctx* c, size_t off) { return reinterpret_cast<P*>(c->ws + off); }
 
 DevScalars* scal_ptr(kf_ctx* c) { return ws_ptr<DevScalars>(c, c->lay.scal); }
+
+// Filter-state buffer b (b = 1 exists only with frame pipelining).
+char* rho_buf(kf_ctx* c, int b) { return c->ws + (b ? c->lay.rho2 : c->lay.rho); }
+char* var_buf(kf_ctx* c, int b) { return c->ws + (b ? c->lay.var2 : c->lay.var); }
+
+// With frame pipelining: the user stream waits for the solves enqueued on the
+// solve stream (they run in order, so waiting for the last one suffices).
+hipError_t wait_solves(kf_ctx* c) {
+  if (c->last_solve < 0) return hipSuccess;
+  return hipStreamWaitEvent(c->stream, c->ev_solve[c->last_solve], 0);
+}
 
 // General 4x4 inverse (Gauss-Jordan, partial pivoting), row-major.
 bool inv4(const double* m, double* out) {
@@ -276,8 +291,10 @@ bool stereo_args(kf_ctx* c, const uint8_t* image1, const double* T_wc1, StereoAr
   a->list = ws_ptr<int32_t>(c, c->lay.list);
   a->scal_ro = scal_ptr(c);
   a->scal = scal_ptr(c);
-  a->rho = c->ws + c->lay.rho;
-  a->var = c->ws + c->lay.var;
+  a->rho = rho_buf(c, c->cur);
+  a->var = var_buf(c, c->cur);
+  a->rho_out = a->rho;
+  a->var_out = a->var;
   a->match = ws_ptr<int32_t>(c, c->lay.match);
   return true;
 }
@@ -301,8 +318,8 @@ void solve_args(kf_ctx* c, SolveArgs* a) {
   a->tile_w = c->tiling.tile_w;
   a->tile_h = c->tiling.tile_h;
   a->prior = c->ws + c->lay.prior;
-  a->rho = c->ws + c->lay.rho;
-  a->var = c->ws + c->lay.var;
+  a->rho = rho_buf(c, c->cur);
+  a->var = var_buf(c, c->cur);
   a->x = c->ws + c->lay.x;
   a->scal = scal_ptr(c);
   a->parts = ws_ptr<uint64_t>(c, c->lay.parts);
@@ -410,11 +427,29 @@ kf_status kf_create(const kf_config* cfg, kf_ctx** out) {
   c->timeout_ticks = (uint64_t)((double)rate_khz * timeout_ms);   // wall-clock ticks
   c->stereo_blocks = stereo_grid_blocks(c->device);
   c->coresident = -1;
+  if (cfg->pipeline_frames) {
+    hipError_t e = hipStreamCreateWithFlags(&c->solve_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_user, hipEventDisableTiming);
+    for (int b = 0; b < 2 && e == hipSuccess; ++b) e = hipEventCreateWithFlags(&c->ev_solve[b], hipEventDisableTiming);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      kf_destroy(c);
+      return KF_ERR_HIP;
+    }
+  }
   *out = c;
   return KF_OK;
 }
 
-void kf_destroy(kf_ctx* ctx) { delete ctx; }
+void kf_destroy(kf_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->solve_stream) (void)hipStreamSynchronize(ctx->solve_stream);
+  for (hipEvent_t ev : ctx->ev_solve)
+    if (ev) (void)hipEventDestroy(ev);
+  if (ctx->ev_user) (void)hipEventDestroy(ctx->ev_user);
+  if (ctx->solve_stream) (void)hipStreamDestroy(ctx->solve_stream);
+  delete ctx;
+}
 
 const char* kf_last_error(const kf_ctx* ctx) {
   if (!ctx) return "no context";
@@ -443,8 +478,12 @@ kf_status kf_set_prior(kf_ctx* c, const uint8_t* image0, const void* logdepth, c
   if (!pose_ok(T_wc0)) return fail(c, KF_ERR_ARG, "kf_set_prior: pose must be finite with last row 0 0 0 1");
   std::memcpy(c->T_wc0, T_wc0, sizeof(c->T_wc0));
   // exchange words and device scalars start from zero (epoch 0 is never used)
-  hipError_t e = launch_zero(c->ws + c->lay.scal, c->lay.total - c->lay.scal, c->stream);
+  hipError_t e = wait_solves(c);
+  if (e == hipSuccess) e = launch_zero(c->ws + c->lay.scal, c->lay.total - c->lay.scal, c->stream);
+  if (e == hipSuccess && c->lay.match > c->lay.rho2)   // second filter-state buffer
+    e = launch_zero(c->ws + c->lay.rho2, c->lay.match - c->lay.rho2, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "kf_set_prior (clear)");
+  c->cur = 0;
   c->epoch = 1;
   PriorArgs a;
   a.W = c->cfg.width;
@@ -454,8 +493,8 @@ kf_status kf_set_prior(kf_ctx* c, const uint8_t* image0, const void* logdepth, c
   a.i0 = c->ws + c->lay.i0;
   a.prior = c->ws + c->lay.prior;
   a.x = c->ws + c->lay.x;
-  a.rho = c->ws + c->lay.rho;
-  a.var = c->ws + c->lay.var;
+  a.rho = rho_buf(c, 0);
+  a.var = var_buf(c, 0);
   a.match = ws_ptr<int32_t>(c, c->lay.match);
   a.chunk_counts = ws_ptr<int32_t>(c, c->lay.chunk);
   a.list = ws_ptr<int32_t>(c, c->lay.list);
@@ -476,10 +515,20 @@ kf_status kf_stereo_update(kf_ctx* c, const uint8_t* image1, const double T_wc1[
   if (!pose_ok(T_wc1)) return fail(c, KF_ERR_ARG, "kf_stereo_update: pose must be finite with last row 0 0 0 1");
   StereoArgs a;
   if (!stereo_args(c, image1, T_wc1, &a)) return fail(c, KF_ERR_ARG, "kf_stereo_update: singular pose");
-  hipError_t e = launch_zero(&scal_ptr(c)->n_updated, sizeof(int32_t), c->stream);
+  hipError_t e = hipSuccess;
+  const int nxt = c->cur ^ 1;
+  if (c->cfg.pipeline_frames) {
+    // read the state the last update wrote, write the other buffer, which the
+    // solve before last may still be reading
+    a.rho_out = rho_buf(c, nxt);
+    a.var_out = var_buf(c, nxt);
+    if (c->solve_pending[nxt]) e = hipStreamWaitEvent(c->stream, c->ev_solve[nxt], 0);
+  }
+  if (e == hipSuccess) e = launch_zero(&scal_ptr(c)->n_updated, sizeof(int32_t), c->stream);
   if (e == hipSuccess)
     e = launch_stereo(c->cfg.precision, c->cfg.pattern, c->cfg.n_samples, a, c->stereo_blocks, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "kf_stereo_update");
+  if (c->cfg.pipeline_frames) c->cur = nxt;
   ++c->frame;
   return KF_OK;
 }
@@ -489,7 +538,10 @@ kf_status kf_solve(kf_ctx* c) {
   if (!c->has_prior) return fail(c, KF_ERR_STATE, "kf_solve before kf_set_prior");
   const kf_config& g = c->cfg;
   const uint32_t bound = solve_epoch_bound(g);
-  hipError_t e = epoch_wrap_if_needed(c, bound);
+  hipError_t e = hipSuccess;
+  // the epoch restart clears words the previous solve may still use
+  if (g.pipeline_frames && (uint64_t)c->epoch + bound >= 0xfff00000ull) e = wait_solves(c);
+  if (e == hipSuccess) e = epoch_wrap_if_needed(c, bound);
   if (e != hipSuccess) return hip_fail(c, e, "kf_solve (epoch wrap)");
   SolveArgs a;
   solve_args(c, &a);
@@ -498,7 +550,21 @@ kf_status kf_solve(kf_ctx* c) {
   if (c->coresident < c->tiling.blocks)
     return fail(c, KF_ERR_ARG, "solver tiling needs " + std::to_string(c->tiling.blocks) +
                                " co-resident workgroups, the device holds " + std::to_string(c->coresident));
-  e = launch_solve(g.precision, c->tiling, a, g.solver_cooperative != 0, pipelined, c->stream);
+  hipStream_t s = c->stream;
+  if (g.pipeline_frames) {
+    // the solve waits for everything enqueued on the user stream so far (this
+    // frame's stereo update included), not the other way round
+    s = c->solve_stream;
+    e = hipEventRecord(c->ev_user, c->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, c->ev_user, 0);
+    if (e != hipSuccess) return hip_fail(c, e, "kf_solve (ordering)");
+  }
+  e = launch_solve(g.precision, c->tiling, a, g.solver_cooperative != 0, pipelined, s);
+  if (e == hipSuccess && g.pipeline_frames) {
+    e = hipEventRecord(c->ev_solve[c->cur], s);
+    c->solve_pending[c->cur] = true;
+    c->last_solve = c->cur;
+  }
   if (e != hipSuccess) return hip_fail(c, e, "kf_solve");
   c->epoch += bound;
   return KF_OK;
@@ -513,12 +579,13 @@ kf_status kf_fuse_frame(kf_ctx* c, const uint8_t* image1, const double T_wc1[16]
 kf_status kf_read_depth(kf_ctx* c, void* depth_out, void* var_out, double* scale_out) {
   if (!c) return KF_ERR_ARG;
   if (!c->has_prior) return fail(c, KF_ERR_STATE, "kf_read_depth before kf_set_prior");
+  if (hipError_t e = wait_solves(c); e != hipSuccess) return hip_fail(c, e, "kf_read_depth");
   if (depth_out || var_out) {
     if (!depth_out) return fail(c, KF_ERR_ARG, "kf_read_depth: var_out needs depth_out");
     ReadArgs a;
     a.N = c->cfg.width * c->cfg.height;
     a.x = c->ws + c->lay.x;
-    a.var = c->ws + c->lay.var;
+    a.var = var_buf(c, c->cur);
     a.depth_out = depth_out;
     a.var_out = var_out;
     hipError_t e = launch_read(c->cfg.precision, a, c->stream);
@@ -539,7 +606,8 @@ kf_status kf_read_stats(kf_ctx* c, kf_frame_stats* out) {
   if (!c || !out) return KF_ERR_ARG;
   if (!c->has_prior) return fail(c, KF_ERR_STATE, "kf_read_stats before kf_set_prior");
   DevScalars h;
-  hipError_t e = hipMemcpyAsync(&h, scal_ptr(c), sizeof(h), hipMemcpyDeviceToHost, c->stream);
+  hipError_t e = wait_solves(c);
+  if (e == hipSuccess) e = hipMemcpyAsync(&h, scal_ptr(c), sizeof(h), hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "kf_read_stats");
   out->n_searched = h.mask_count;
@@ -552,6 +620,8 @@ kf_status kf_read_stats(kf_ctx* c, kf_frame_stats* out) {
   if (h.err & ERR_INPUT) return fail(c, KF_ERR_INPUT, "device found a non-finite input or a variance <= 0");
   return KF_OK;
 }
+
+void* kf_solve_stream(const kf_ctx* c) { return c ? reinterpret_cast<void*>(c->solve_stream) : nullptr; }
 
 kf_status kf_solver_layout(const kf_ctx* c, int32_t out[5]) {
   if (!c || !out) return KF_ERR_ARG;
@@ -568,11 +638,11 @@ kf_status kf_export_state(kf_ctx* c, void* x, void* rho, void* rho_var, int32_t*
   if (!c->has_prior) return fail(c, KF_ERR_STATE, "kf_export_state before kf_set_prior");
   const size_t N = (size_t)c->cfg.width * c->cfg.height;
   const size_t nb = N * c->lay.elt;
-  hipError_t e = hipSuccess;
+  hipError_t e = wait_solves(c);
   if (x && e == hipSuccess) e = hipMemcpyAsync(x, c->ws + c->lay.x, nb, hipMemcpyDeviceToDevice, c->stream);
-  if (rho && e == hipSuccess) e = hipMemcpyAsync(rho, c->ws + c->lay.rho, nb, hipMemcpyDeviceToDevice, c->stream);
+  if (rho && e == hipSuccess) e = hipMemcpyAsync(rho, rho_buf(c, c->cur), nb, hipMemcpyDeviceToDevice, c->stream);
   if (rho_var && e == hipSuccess)
-    e = hipMemcpyAsync(rho_var, c->ws + c->lay.var, nb, hipMemcpyDeviceToDevice, c->stream);
+    e = hipMemcpyAsync(rho_var, var_buf(c, c->cur), nb, hipMemcpyDeviceToDevice, c->stream);
   if (match && e == hipSuccess)
     e = hipMemcpyAsync(match, c->ws + c->lay.match, N * 4, hipMemcpyDeviceToDevice, c->stream);
   double t = 0.0;
@@ -588,14 +658,14 @@ kf_status kf_import_state(kf_ctx* c, const void* x, const void* rho, const void*
   if (!c->has_prior) return fail(c, KF_ERR_STATE, "kf_import_state before kf_set_prior");
   if ((rho == nullptr) != (rho_var == nullptr)) return fail(c, KF_ERR_ARG, "kf_import_state: rho and rho_var go together");
   if (tau && !std::isfinite(*tau)) return fail(c, KF_ERR_ARG, "kf_import_state: tau must be finite");
-  hipError_t e = hipSuccess;
-  if (x || rho) {
+  hipError_t e = wait_solves(c);
+  if ((x || rho) && e == hipSuccess) {
     ImportArgs a;
     a.N = c->cfg.width * c->cfg.height;
     a.x = x; a.rho = rho; a.var = rho_var;
     a.dx = c->ws + c->lay.x;
-    a.drho = c->ws + c->lay.rho;
-    a.dvar = c->ws + c->lay.var;
+    a.drho = rho_buf(c, c->cur);
+    a.dvar = var_buf(c, c->cur);
     a.scal = scal_ptr(c);
     e = launch_import(c->cfg.precision, a, c->stream);
   }

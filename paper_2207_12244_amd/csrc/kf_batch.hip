@@ -273,7 +273,7 @@ kf_status kf_batch_create(kf_ctx* const* members, int32_t n, const kf_batch_conf
   const kf_ctx* c0 = members[0];
   for (int i = 0; i < n; ++i) {
     const kf_ctx* c = members[i];
-    if (c->cfg.precision != c0->cfg.precision || c->cfg.pattern != c0->cfg.pattern ||
+    if (c->cfg.pipeline_frames || c->cfg.precision != c0->cfg.precision || c->cfg.pattern != c0->cfg.pattern ||
         c->cfg.n_samples != c0->cfg.n_samples || c->tiling.threads != c0->tiling.threads ||
         solve_pipelined(c->cfg) != solve_pipelined(c0->cfg) || c->device != c0->device ||
         c->stream != reinterpret_cast<hipStream_t>(cfg->stream))

@@ -97,7 +97,7 @@ enum : int32_t { ERR_INPUT = 1, ERR_TIMEOUT = 2 };
 // ------------------------------------------------------------------ workspace layout
 
 struct Layout {
-  size_t i0, list, chunk, prior, x, rho, var, match, i1s, scal, parts, halo, total;
+  size_t i0, list, chunk, prior, x, rho, var, rho2, var2, match, i1s, scal, parts, halo, total;
   size_t elt;       // sizeof(T)
   size_t elt_img;   // sizeof(TI)
 };
@@ -153,7 +153,9 @@ struct StereoArgs {
   const int32_t* list;
   const DevScalars* scal_ro;
   DevScalars* scal;
-  void* rho; void* var; int32_t* match;
+  void* rho; void* var;       // filter state read
+  void* rho_out; void* var_out;   // filter state written (== rho / var: in place)
+  int32_t* match;
   FrameConst fc;
 };
 
@@ -230,6 +232,15 @@ struct kf_ctx {
   uint64_t timeout_ticks;
   int stereo_blocks;
   int coresident;      // workgroups of the solver tiling the device holds at once (-1: not checked)
+  // frame pipelining (cfg.pipeline_frames): the solve runs on solve_stream, the
+  // filter state alternates between two buffers, cur = the one the last stereo
+  // update wrote (and the next solve reads)
+  int cur = 0;
+  hipStream_t solve_stream = nullptr;
+  hipEvent_t ev_user = nullptr;           // user stream's tail when a solve is enqueued
+  hipEvent_t ev_solve[2] = {nullptr, nullptr};   // last solve that read buffer b
+  bool solve_pending[2] = {false, false};
+  int last_solve = -1;                    // buffer of the last enqueued solve
 };
 
 namespace kf {

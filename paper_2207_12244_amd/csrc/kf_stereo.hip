@@ -248,8 +248,10 @@ __device__ inline bool stereo_pixel(const StereoArgs& a, int idx, bool active, i
   const int grp = lane / G;
   const int gl = lane % G;
   const KF_GLOBAL TI* i0 = gp(static_cast<const TI*>(a.i0));
-  KF_GLOBAL T* rho_s = gp(static_cast<T*>(a.rho));
-  KF_GLOBAL T* var_s = gp(static_cast<T*>(a.var));
+  const KF_GLOBAL T* rho_s = gp(static_cast<const T*>(a.rho));
+  const KF_GLOBAL T* var_s = gp(static_cast<const T*>(a.var));
+  KF_GLOBAL T* rho_o = gp(static_cast<T*>(a.rho_out));
+  KF_GLOBAL T* var_o = gp(static_cast<T*>(a.var_out));
   const int W = a.W, H = a.H;
   const int st = a.i1_stride;
   bool updated = false;
@@ -409,14 +411,18 @@ __device__ inline bool stereo_pixel(const StereoArgs& a, int idx, bool active, i
       if (isfinite((double)var_d) && var_d > (T)0 && isfinite((double)dstar) && dstar > (T)0 &&
           isfinite((double)vo) && vo > (T)0) {
         if (has) {   // Gaussian product with the current estimate
-          rho_s[pix] = (vo * rho0 + var0 * ro) / (var0 + vo);
-          var_s[pix] = var0 * vo / (var0 + vo);
+          rho_o[pix] = (vo * rho0 + var0 * ro) / (var0 + vo);
+          var_o[pix] = var0 * vo / (var0 + vo);
         } else {
-          rho_s[pix] = ro;
-          var_s[pix] = vo;
+          rho_o[pix] = ro;
+          var_o[pix] = vo;
         }
         updated = true;
       }
+    }
+    if (!updated && a.rho_out != a.rho) {   // double-buffered state: carry the estimate over
+      rho_o[pix] = rho0;
+      var_o[pix] = var0;
     }
   }
   return updated;

@@ -48,7 +48,8 @@ class KfConfig(ctypes.Structure):
         ("grad_gate", c_double), ("sigma_photo", c_double), ("r_floor", c_double),
         ("precision", c_int32),
         ("solver_tiles_x", c_int32), ("solver_tiles_y", c_int32),
-        ("solver_threads", c_int32), ("solver_cooperative", c_int32), ("solver_timeout_ms", c_double),
+        ("solver_threads", c_int32), ("solver_cooperative", c_int32), ("pipeline_frames", c_int32),
+        ("solver_timeout_ms", c_double),
         ("stream", c_void_p), ("workspace", c_void_p), ("workspace_bytes", c_size_t),
     ]
 
@@ -104,6 +105,7 @@ def load_library(path: Optional[str] = None):
         "kf_read_stats": (c_int32, [P, POINTER(KfFrameStats)]),
         "kf_export_state": (c_int32, [P, P, P, P, P, POINTER(c_double)]),
         "kf_solver_layout": (c_int32, [P, POINTER(c_int32)]),
+        "kf_solve_stream": (c_void_p, [P]),
         "kf_import_state": (c_int32, [P, P, P, P, POINTER(c_double)]),
         "kf_batch_config_default": (None, [POINTER(KfBatchConfig)]),
         "kf_batch_workspace_bytes": (c_size_t, [POINTER(P), c_int32]),
@@ -127,7 +129,7 @@ def load_library(path: Optional[str] = None):
 EXPORTED_SYMBOLS = (
     "kf_config_default", "kf_workspace_bytes", "kf_create", "kf_destroy", "kf_last_error", "kf_status_string",
     "kf_set_prior", "kf_stereo_update", "kf_solve", "kf_fuse_frame", "kf_read_depth", "kf_read_stats",
-    "kf_export_state", "kf_import_state", "kf_solver_layout",
+    "kf_export_state", "kf_import_state", "kf_solver_layout", "kf_solve_stream",
     "kf_batch_config_default", "kf_batch_workspace_bytes", "kf_batch_create", "kf_batch_fuse",
     "kf_batch_fuse_subset", "kf_batch_stereo_update", "kf_batch_solve", "kf_batch_layout",
     "kf_batch_last_error", "kf_batch_destroy",
@@ -315,7 +317,8 @@ class Keyframe:
                  n_samples: int = 32, n_gn: int = 10, n_cg: int = 20, cg_rtol: float = 0.0, cg_max: int = 4000,
                  huber_delta: float = 1.345, d_near: float = 0.4, d_far: float = 10.0, grad_gate: float = 6.0,
                  sigma_photo: float = 1.0, r_floor: float = 1e-6, K=None, tiles=(0, 0), solver_threads: int = 0,
-                 cooperative: bool = False, cg_variant: str = "auto", solver_timeout_ms: float = 0.0, stream=None):
+                 cooperative: bool = False, cg_variant: str = "auto", solver_timeout_ms: float = 0.0,
+                 pipeline_frames: bool = False, stream=None):
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("Keyframe needs a GPU (the library has no CPU path)")
@@ -333,6 +336,7 @@ class Keyframe:
         cfg.solver_threads, cfg.solver_cooperative = int(solver_threads), int(bool(cooperative))
         cfg.cg_variant = {"auto": 0, "textbook": 1, "pipelined": 2}[cg_variant]
         cfg.solver_timeout_ms = float(solver_timeout_ms)
+        cfg.pipeline_frames = int(bool(pipeline_frames))
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         cfg.stream = c_void_p(self.stream.cuda_stream)
         nbytes = kf_workspace_bytes(cfg)
@@ -398,6 +402,12 @@ class Keyframe:
 
     def solver_layout(self):
         return kf_solver_layout(self.ctx)
+
+    def solve_stream(self):
+        """torch stream the solves run on (pipeline_frames), else the context's stream."""
+        torch = _torch()
+        h = load_library().kf_solve_stream(self.ctx)
+        return torch.cuda.ExternalStream(h) if h else self.stream
 
     def stats(self) -> KfFrameStats:
         return kf_read_stats(self.ctx)

@@ -290,3 +290,32 @@ def test_end_to_end_config0(c0):
     x_d, _, _ = fusion.gauss_newton(ok.prior.mu, 0.0, ok.prior, ok.semi(), SolverParams(n_gn=10, linear_solver="direct"))
     gu.say(f"[e2e-c0] vs direct solves max|dlogd| {np.abs(np.log(d.cpu().numpy()) - x_d).max():.3e}")
     assert np.abs(np.log(d.cpu().numpy()) - x_d).max() <= 5e-9
+
+
+def test_frame_pipelining_gives_the_same_results(c1_short):
+    """pipeline_frames = 1 (solve on a second stream, double-buffered filter
+    state, next stereo overlapping the solve) ends bit-identical to one stream,
+    with reads in between frames."""
+    t = gu.torch()
+    case = kfsynth.config_case(1, 0, frames=4)
+    outs = []
+    for pipe in (False, True):
+        from paper_2207_12244_amd.kf import Keyframe
+        kf = Keyframe(case.W, case.H, precision="f32", pattern="sq5x5", n_samples=64, n_gn=10, n_cg=20, K=case.K,
+                      pipeline_frames=pipe)
+        kf.set_prior(gu.dev(case.image0, t.uint8), *[gu.dev(m, t.float32) for m in case.priors.maps()],
+                     case.T_wc0)
+        imgs = [gu.dev(im, t.uint8) for im in case.images]
+        mids = []
+        for f in range(4):
+            kf.fuse_frame(imgs[f], case.poses[f])
+            if f == 1:
+                mids.append(kf.export_state())
+        st = kf.stats()
+        outs.append((kf.export_state(), mids, st.n_updated, st.n_valid))
+        gu.say(f"[pipeline={pipe}] n_updated {st.n_updated} n_valid {st.n_valid} scale {st.scale:.6f}")
+    (a, ma, ua, va), (b, mb, ub, vb) = outs
+    for k in ("x", "rho", "var", "match"):
+        assert np.array_equal(a[k].cpu().numpy(), b[k].cpu().numpy()), k
+        assert np.array_equal(ma[0][k].cpu().numpy(), mb[0][k].cpu().numpy()), k
+    assert a["tau"] == b["tau"] and (ua, va) == (ub, vb)
