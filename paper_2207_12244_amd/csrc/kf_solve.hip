@@ -188,12 +188,20 @@ struct Team {
       else Wire<double>::put(part_slot(e, v, b, r), p, e);
     }
     pre();
-    // poll set of this thread
-    const int nslots = nv * B;
+    // poll set of this thread: slot s = (value v, member j) with the members of
+    // each value padded to a multiple of 64 slots, so that every wavefront
+    // polls slots of one value only and can reduce them itself
+    const int Bp = (B + 63) & ~63;
+    const int nslots = nv * Bp;
     bool p_ready[PSLOTS], g_ready[GMAX];
     uint64_t pw0[PSLOTS], pw1[PSLOTS], gw0[GMAX], gw1[GMAX];
+    double pval[PSLOTS];
 #pragma unroll
-    for (int q = 0; q < PSLOTS; ++q) p_ready[q] = tid + q * NT >= nslots;
+    for (int q = 0; q < PSLOTS; ++q) {
+      const int sl = tid + q * NT;
+      pval[q] = 0.0;
+      p_ready[q] = sl >= nslots || sl % Bp >= B;
+    }
 #pragma unroll
     for (int m = 0; m < GMAX; ++m) g_ready[m] = !(ghosts && g_src[m] >= 0);
     unsigned spins = 0;
@@ -204,7 +212,7 @@ struct Team {
 #pragma unroll
       for (int q = 0; q < PSLOTS; ++q) {
         if (!p_ready[q]) {
-          const int s = tid + q * NT, v = s / B, j = s - v * B;
+          const int s = tid + q * NT, v = s / Bp, j = s - v * Bp;
           const KF_GLOBAL uint64_t* w = part_slot(e, v, j, b % PART_REPLICAS);
           pw0[q] = ld_word(w);
           if (!packed) pw1[q] = ld_word(w + 1);
@@ -224,9 +232,7 @@ struct Team {
           if (packed ? Packed48::ready(pw0[q], e)
                      : ((uint32_t)(pw0[q] >> 32) == e && (uint32_t)(pw1[q] >> 32) == e)) {
             p_ready[q] = true;
-            const int s = tid + q * NT, v = s / B, j = s - v * B;
-            s_pol[v * B + j] = packed ? Packed48::value(pw0[q])
-                                      : Wire<double>::make((uint32_t)pw0[q], (uint32_t)pw1[q]);
+            pval[q] = packed ? Packed48::value(pw0[q]) : Wire<double>::make((uint32_t)pw0[q], (uint32_t)pw1[q]);
           } else {
             all = false;
           }
@@ -259,13 +265,25 @@ struct Team {
       *s_abort = 1;
       __hip_atomic_fetch_or(err, ERR_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    // each wavefront sums its 64 polled slots (one value, fixed order) into a
+    // chunk partial; the chunk index is wavefront-uniform
+#pragma unroll
+    for (int q = 0; q < PSLOTS; ++q) {
+      const int chunk = (q * NT + tid) >> 6;
+      if (chunk * 64 < nslots) {
+        const double cs = wave_sum(pval[q]);
+        if (lane == 0) s_pol[chunk] = cs;
+      }
+    }
     __syncthreads();
     if (*s_abort) return false;
-    // every wavefront forms the totals (fixed order, no third barrier)
+    // every wavefront forms the totals from the chunk partials (fixed order,
+    // so all threads of all workgroups hold bit-identical totals)
+    const int cpv = Bp >> 6;   // chunks per value
     for (int v = 0; v < nv; ++v) {
       double acc = 0.0;
-      for (int j = lane; j < B; j += 64) acc += s_pol[v * B + j];
-      tot[v] = wave_sum(acc);
+      for (int c = 0; c < cpv; ++c) acc += s_pol[v * cpv + c];
+      tot[v] = acc;
     }
     return true;
   }
