@@ -119,6 +119,7 @@ template <typename T, int NT>
 struct Team {
   static constexpr int NW = NT / 64;
   static constexpr int PSLOTS = (NV_MAX * MAX_TEAM + NT - 1) / NT;   // partial slots polled per thread
+  static constexpr int CPV = MAX_TEAM / 64;                            // 64-slot chunks per value, at most
   int B, b, tw, th, rw, perim, tile_w, tile_h;
   int nb_up, nb_dn, nb_lf, nb_rt;
   KF_GLOBAL uint64_t* parts;
@@ -127,7 +128,7 @@ struct Team {
   uint64_t limit;
   bool packed;      // one-word partials (Packed48) instead of two words
   double* s_wred;   // [NW][NV_MAX]
-  double* s_pol;    // [NV_MAX][B]
+  double* s_pol;    // [NV_MAX][CPV] chunk partials (unused chunks stay 0)
   int* s_abort;
   // ghost slots of this thread
   int g_src[GMAX];  // neighbour workgroup or -1
@@ -153,10 +154,11 @@ struct Team {
   }
 
   // Team-wide sums of nv per-thread partials and, if `ghosts`, the neighbours'
-  // published boundary values for this thread's ghost slots. Every wavefront
-  // sums the team's partials itself in the same fixed order, so all threads of
-  // all workgroups hold bit-identical totals. All words a thread waits for are
-  // loaded together each polling round. Returns false if the team aborts.
+  // published boundary values for this thread's ghost slots. Each wavefront
+  // reduces the 64 team partials it polled; every wavefront then adds those
+  // chunk sums in the same fixed order, so all threads of all workgroups hold
+  // bit-identical totals. All words a thread waits for are loaded together
+  // each polling round. Returns false if the team aborts.
   __device__ bool sync(uint32_t e, int nv, const double* vals, double* tot, T* gval, bool ghosts, T* ring = nullptr) {
     return sync(e, nv, vals, tot, gval, ghosts, ring, [] {});
   }
@@ -195,7 +197,7 @@ struct Team {
     const int nslots = nv * Bp;
     bool p_ready[PSLOTS], g_ready[GMAX];
     uint64_t pw0[PSLOTS], pw1[PSLOTS], gw0[GMAX], gw1[GMAX];
-    double pval[PSLOTS];
+    double pval[PSLOTS];   // decoded partials; padding slots keep 0
 #pragma unroll
     for (int q = 0; q < PSLOTS; ++q) {
       const int sl = tid + q * NT;
@@ -267,22 +269,28 @@ struct Team {
     }
     // each wavefront sums its 64 polled slots (one value, fixed order) into a
     // chunk partial; the chunk index is wavefront-uniform
+    const int cpv = Bp >> 6;   // chunks per value
 #pragma unroll
     for (int q = 0; q < PSLOTS; ++q) {
       const int chunk = (q * NT + tid) >> 6;
       if (chunk * 64 < nslots) {
         const double cs = wave_sum(pval[q]);
-        if (lane == 0) s_pol[chunk] = cs;
+        const int v = chunk / cpv;
+        if (lane == 0) s_pol[v * CPV + chunk - v * cpv] = cs;
       }
     }
     __syncthreads();
     if (*s_abort) return false;
     // every wavefront forms the totals from the chunk partials (fixed order,
-    // so all threads of all workgroups hold bit-identical totals)
-    const int cpv = Bp >> 6;   // chunks per value
+    // so all threads of all workgroups hold bit-identical totals); the
+    // chunks past cpv hold zeros, so all CPV loads issue together
     for (int v = 0; v < nv; ++v) {
-      double acc = 0.0;
-      for (int c = 0; c < cpv; ++c) acc += s_pol[v * cpv + c];
+      double c[CPV];
+#pragma unroll
+      for (int k = 0; k < CPV; ++k) c[k] = s_pol[v * CPV + k];
+      double acc = c[0];
+#pragma unroll
+      for (int k = 1; k < CPV; ++k) acc += c[k];
       tot[v] = acc;
     }
     return true;
@@ -319,14 +327,14 @@ __device__ __forceinline__ void solve_member(const SolveArgs& a, const int b, un
   tm.err = &scal->err;
   tm.limit = a.timeout_ticks;
   tm.packed = a.packed != 0;
-  // LDS: [NW][NV_MAX] wave partials, [NV_MAX][B] team partials, abort flag,
+  // LDS: [NW][NV_MAX] wave partials, [NV_MAX][CPV] team chunk partials, abort flag,
   // then three rings of (tile_h + 2) x (tile_w + 2): x, and two stencil operands
   double* dsm = reinterpret_cast<double*>(smem);
   tm.s_wred = dsm;
   tm.s_pol = tm.s_wred + NW * NV_MAX;
-  tm.s_abort = reinterpret_cast<int*>(tm.s_pol + NV_MAX * B);
+  tm.s_abort = reinterpret_cast<int*>(tm.s_pol + NV_MAX * Team<T, NT>::CPV);
   const int ring_max = (a.tile_h + 2) * (a.tile_w + 2);
-  T* xs = reinterpret_cast<T*>(dsm + NW * NV_MAX + NV_MAX * B + 2);
+  T* xs = reinterpret_cast<T*>(dsm + NW * NV_MAX + NV_MAX * Team<T, NT>::CPV + 2);
   T* ps = xs + ring_max;
   T* ms0 = ps + ring_max;
 
@@ -335,6 +343,7 @@ __device__ __forceinline__ void solve_member(const SolveArgs& a, const int b, un
   const T delta = (T)a.huber_delta;
 
   for (int i = tid; i < 3 * ring_max; i += NT) xs[i] = (T)0;
+  if (tid < NV_MAX * Team<T, NT>::CPV) tm.s_pol[tid] = 0.0;
   if (tid == 0) *tm.s_abort = 0;
 
   // ghost slots: top row, bottom row, left column, right column
@@ -698,11 +707,12 @@ __global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
 // Batched form: workgroup g works through its queue of (keyframe, member)
 // entries in order. Queues list teams in one global order, so the lowest
 // unfinished team always has every member at it and the launch cannot
-// deadlock, provided all workgroups are co-resident. 512-thread workgroups of
-// up to 4 pixels per thread are held to 128 registers so that two of them
-// share a compute unit (one computes while the other's team synchronises).
+// deadlock, provided all workgroups are co-resident. FP32 512-thread
+// workgroups of up to 4 pixels per thread are held to 128 registers so that two
+// of them share a compute unit (one computes while the other's team
+// synchronises).
 template <typename T, int NT, int PPT, bool PIPE>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 512 && NT * PPT <= 2048 ? 4 : 1)))
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && NT == 512 && NT * PPT <= 2048 ? 4 : 1)))
 void k_solve_batch(const SolveArgs* __restrict__ tab,
                                                     const int32_t* __restrict__ queue,
                                                     const int32_t* __restrict__ qoff) {
@@ -733,7 +743,7 @@ namespace {
 
 size_t smem_for(size_t elt, const Tiling& t) {
   const size_t ring = (size_t)(t.tile_h + 2) * (t.tile_w + 2);
-  return sizeof(double) * ((size_t)(t.threads / 64) * NV_MAX + NV_MAX * (size_t)t.blocks + 2) + 3 * ring * elt;
+  return sizeof(double) * ((size_t)(t.threads / 64) * NV_MAX + NV_MAX * (MAX_TEAM / 64) + 2) + 3 * ring * elt;
 }
 
 template <typename T, bool PIPE>
