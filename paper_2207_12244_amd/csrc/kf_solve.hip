@@ -153,21 +153,47 @@ struct Team {
     if (lx == tw - 1 && nb_rt >= 0) Wire<T>::put(halo_slot(e, b, 2 * tile_w + tile_h + ly), val, e);
   }
 
+  // Publishes the whole tile boundary from the ring that holds the own values
+  // (after a barrier): thread s writes boundary slot s, so only the first
+  // perimeter's worth of threads issue the stores.
+  __device__ void publish_ring(uint32_t e, const T* ring) const {
+    int s = threadIdx.x;
+    refresh(s);
+    for (; s < perim; s += NT) {
+      int lx, ly, nb;
+      if (s < tile_w) {
+        lx = s; ly = 0; nb = nb_up;
+      } else if (s < 2 * tile_w) {
+        lx = s - tile_w; ly = th - 1; nb = nb_dn;
+      } else if (s < 2 * tile_w + tile_h) {
+        lx = 0; ly = s - 2 * tile_w; nb = nb_lf;
+      } else {
+        lx = tw - 1; ly = s - 2 * tile_w - tile_h; nb = nb_rt;
+      }
+      if (nb >= 0 && lx < tw && ly < th) Wire<T>::put(halo_slot(e, b, s), ring[(ly + 1) * rw + lx + 1], e);
+    }
+  }
+
   // Team-wide sums of nv per-thread partials and, if `ghosts`, the neighbours'
-  // published boundary values for this thread's ghost slots. Each wavefront
-  // reduces the 64 team partials it polled; every wavefront then adds those
-  // chunk sums in the same fixed order, so all threads of all workgroups hold
-  // bit-identical totals. All words a thread waits for are loaded together
-  // each polling round. Returns false if the team aborts.
-  __device__ bool sync(uint32_t e, int nv, const double* vals, double* tot, T* gval, bool ghosts, T* ring = nullptr) {
-    return sync(e, nv, vals, tot, gval, ghosts, ring, [] {});
+  // published boundary values for this thread's ghost slots (stored into
+  // `ring` too when given). With `ring_pub` the own boundary is published from
+  // `ring` (the caller wrote its own values there), otherwise the caller has
+  // published it. Each wavefront reduces the 64 team partials it polled;
+  // every wavefront then adds those chunk sums in the same fixed order, so all
+  // threads of all workgroups hold bit-identical totals. All words a thread
+  // waits for are loaded together each polling round. Returns false if the
+  // team aborts.
+  __device__ bool sync(uint32_t e, int nv, const double* vals, double* tot, T* gval, bool ghosts, T* ring = nullptr,
+                       bool ring_pub = false) {
+    return sync(e, nv, vals, tot, gval, ghosts, ring, ring_pub, [] {});
   }
 
   // As above; `pre()` runs in every thread after the workgroup has published
   // its partials and before it polls: work that needs no neighbour data (and
   // may read LDS written before the synchronisation) overlaps the wait.
   template <typename F>
-  __device__ bool sync(uint32_t e, int nv, const double* vals, double* tot, T* gval, bool ghosts, T* ring, F&& pre) {
+  __device__ bool sync(uint32_t e, int nv, const double* vals, double* tot, T* gval, bool ghosts, T* ring, bool ring_pub,
+                       F&& pre) {
     int tid = threadIdx.x;
     refresh(tid);
     const int lane = tid & 63, wave = tid >> 6;
@@ -189,6 +215,7 @@ struct Team {
       if (packed) st_word(part_slot(e, v, b, r), Packed48::make_word(p, e));
       else Wire<double>::put(part_slot(e, v, b, r), p, e);
     }
+    if (ring_pub) publish_ring(e, ring);
     pre();
     // poll set of this thread: slot s = (value v, member j) with the members of
     // each value padded to a multiple of 64 slots, so that every wavefront
@@ -198,11 +225,15 @@ struct Team {
     bool p_ready[PSLOTS], g_ready[GMAX];
     uint64_t pw0[PSLOTS], pw1[PSLOTS], gw0[GMAX], gw1[GMAX];
     double pval[PSLOTS];   // decoded partials; padding slots keep 0
+    const KF_GLOBAL uint64_t* p_addr[PSLOTS];
+    const int cpv = Bp >> 6;   // chunks per value
 #pragma unroll
     for (int q = 0; q < PSLOTS; ++q) {
       const int sl = tid + q * NT;
+      const int v = (sl >> 6) / cpv, j = sl - v * Bp;
       pval[q] = 0.0;
-      p_ready[q] = sl >= nslots || sl % Bp >= B;
+      p_ready[q] = sl >= nslots || j >= B;
+      p_addr[q] = part_slot(e, p_ready[q] ? 0 : v, p_ready[q] ? 0 : j, b % PART_REPLICAS);
     }
 #pragma unroll
     for (int m = 0; m < GMAX; ++m) g_ready[m] = !(ghosts && g_src[m] >= 0);
@@ -214,8 +245,7 @@ struct Team {
 #pragma unroll
       for (int q = 0; q < PSLOTS; ++q) {
         if (!p_ready[q]) {
-          const int s = tid + q * NT, v = s / Bp, j = s - v * Bp;
-          const KF_GLOBAL uint64_t* w = part_slot(e, v, j, b % PART_REPLICAS);
+          const KF_GLOBAL uint64_t* w = p_addr[q];
           pw0[q] = ld_word(w);
           if (!packed) pw1[q] = ld_word(w + 1);
         }
@@ -269,7 +299,6 @@ struct Team {
     }
     // each wavefront sums its 64 polled slots (one value, fixed order) into a
     // chunk partial; the chunk index is wavefront-uniform
-    const int cpv = Bp >> 6;   // chunks per value
 #pragma unroll
     for (int q = 0; q < PSLOTS; ++q) {
       const int chunk = (q * NT + tid) >> 6;
@@ -489,13 +518,12 @@ __device__ __forceinline__ void solve_member(const SolveArgs& a, const int b, un
       const T z = r * idg[j];
       pv[j] = z;
       ps[l] = z;
-      tm.publish(e, KF_LX(j), KF_LY(j), z);
       rz += (double)r * (double)z;
       r2 += (double)r * (double)r;
       b2 += (double)bb * (double)bb;
     }
     vals[0] = rz; vals[1] = r2; vals[2] = b2;
-    if (!tm.sync(e++, tol_mode ? 3 : 1, vals, tot, gval, true, ps)) return;
+    if (!tm.sync(e++, tol_mode ? 3 : 1, vals, tot, gval, true, ps, true)) return;
     double rz_t = tot[0];
     const double bnorm = tol_mode ? sqrt(tot[2]) : 0.0;
     bool converged = false;
@@ -537,7 +565,6 @@ __device__ __forceinline__ void solve_member(const SolveArgs& a, const int b, un
           if (lxy[j] < 0) continue;
           ga += (double)rr[j] * (double)uv[j];
           de += (double)wv[j] * (double)uv[j];
-          tm.publish(e, KF_LX(j), KF_LY(j), mv[j]);
         }
         vals[0] = ga; vals[1] = de;
         // the stencil product of the tile's interior pixels needs no ghost
@@ -559,7 +586,7 @@ __device__ __forceinline__ void solve_member(const SolveArgs& a, const int b, un
           }
         };
         // the neighbours' m lands directly in the ghost ring of mring
-        if (!tm.sync(e++, 2, vals, tot, gval, true, mring, interior)) return;
+        if (!tm.sync(e++, 2, vals, tot, gval, true, mring, true, interior)) return;
         if (tot[0] == 0.0) break;
         double beta = 0.0, alpha;
         if (i > 0) {
@@ -671,11 +698,10 @@ __device__ __forceinline__ void solve_member(const SolveArgs& a, const int b, un
         cnt += 1.0;
       }
       xs[KF_LI(j)] = xr[j];
-      tm.publish(e, KF_LX(j), KF_LY(j), xr[j]);
     }
     vals[0] = num; vals[1] = den; vals[2] = cnt;
     // the neighbours' x lands directly in the ghost ring of xs
-    if (!tm.sync(e++, 3, vals, tot, gval, true, xs)) return;
+    if (!tm.sync(e++, 3, vals, tot, gval, true, xs, true)) return;
     if (tot[1] > 0.0) tau = tot[0] / tot[1];
     n_valid = tot[2];
   }
