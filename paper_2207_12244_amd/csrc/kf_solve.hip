@@ -553,7 +553,11 @@ __device__ __forceinline__ void solve_member(const SolveArgs& a, const int b, un
         mv[j] = w * idg[j];
         ms0[l] = mv[j];
       }
-      double gamma_prev = 1.0, alpha_prev = 1.0;
+      // alpha_i = gamma_i / (delta_i - beta_i gamma_i / alpha_{i-1}); with
+      // den_i = gamma_i / alpha_i the last term is beta_i^2 den_{i-1}, so only
+      // one division (by den_i) waits for the team totals: 1 / gamma_i is
+      // formed beside the vector updates for the next iteration's beta
+      double rgamma_prev = 1.0, den_prev = 1.0;
       for (int i = 0; i < limit && !converged; ++i) {
         T* mring = (i & 1) ? ps : ms0;
         T* mnext = (i & 1) ? ms0 : ps;
@@ -588,15 +592,14 @@ __device__ __forceinline__ void solve_member(const SolveArgs& a, const int b, un
         // the neighbours' m lands directly in the ghost ring of mring
         if (!tm.sync(e++, 2, vals, tot, gval, true, mring, true, interior)) return;
         if (tot[0] == 0.0) break;
-        double beta = 0.0, alpha;
+        double beta = 0.0, den = tot[1];
         if (i > 0) {
-          beta = tot[0] / gamma_prev;
-          alpha = tot[0] / (tot[1] - beta * tot[0] / alpha_prev);
-        } else {
-          alpha = tot[0] / tot[1];
+          beta = tot[0] * rgamma_prev;
+          den = tot[1] - beta * beta * den_prev;
         }
-        gamma_prev = tot[0];
-        alpha_prev = alpha;
+        const double alpha = tot[0] / den;
+        rgamma_prev = 1.0 / tot[0];
+        den_prev = den;
         const T al = (T)alpha, be = (T)beta;
         const bool last = i == limit - 1;
 #pragma unroll
