@@ -164,9 +164,12 @@ def test_solver_parity(c0, precision, mode):
 @pytest.mark.parametrize("precision,threads,tiles,variant", [
     ("f32", 512, (2, 2), "pipelined"), ("f32", 512, (3, 2), "pipelined"), ("f32", 512, (4, 2), "textbook"),
     ("f32", 1024, (4, 2), "pipelined"), ("f32", 256, (4, 3), "pipelined"), ("f64", 256, (4, 4), "pipelined"),
-    ("f64", 512, (4, 3), "textbook"), ("f64", 1024, (5, 4), "pipelined")])
+    ("f64", 512, (4, 3), "textbook"), ("f64", 1024, (5, 4), "pipelined"),
+    # 160 x 6 tiles: a perimeter of 332 boundary slots, more than the 256 threads that publish them
+    ("f32", 256, (1, 20), "pipelined"), ("f64", 256, (1, 20), "textbook")])
 def test_solver_tile_shapes(c0, precision, threads, tiles, variant):
-    """Every workgroup size and pixels-per-thread class of the solver against the oracle."""
+    """Every workgroup size and pixels-per-thread class of the solver against the oracle, and tile
+    shapes whose boundary has more slots than the workgroup has threads."""
     gu.say(f"[solver-shape] config 0 case 0 {precision} {threads} threads tiles {tiles} {variant}")
     rho, var = _oracle_state(c0)
     dt = gu.np_map_dtype(precision)
