@@ -41,7 +41,7 @@ METRIC = "fused keyframe-update Mpixel/s at 640x480 + p50/p99 fuse latency"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "solver_640x480_traffic.json")
 BATCH_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "solver_batched64_traffic.json")
-SOLVER_SRC = os.path.join(ROOT, "paper_2207_12244_amd", "csrc", "kf_solve.hip")
+SOLVER_SRCS = tuple(os.path.join(ROOT, "paper_2207_12244_amd", "csrc", f) for f in ("kf_solve.hip", "kf_internal.h"))
 
 WORKLOAD = dict(config=2, W=640, H=480, frames=30, precision="bf16", pattern="sq5x5", n_samples=128,
                 n_gn=10, n_cg=20)
@@ -57,15 +57,17 @@ def solver_bytes_per_frame(N, n_gn, n_cg, word=4):
     return n_gn * (23 + 9 * n_cg) * word * N
 
 
-def source_hash(path):
-    """sha256 (16 hex) of a source file's code with comments and blank space
+def source_hash(*paths):
+    """sha256 (16 hex) of source files' code with comments and blank space
     removed, so that comment edits do not invalidate counters of an unchanged kernel."""
     import re
-    with open(path) as f:
-        text = f.read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    text = re.sub(r"//[^\n]*", "", text)
-    text = "\n".join(line.strip() for line in text.splitlines() if line.strip())
+    text = ""
+    for path in paths:
+        with open(path) as f:
+            t = f.read()
+        t = re.sub(r"/\*.*?\*/", "", t, flags=re.S)
+        t = re.sub(r"//[^\n]*", "", t)
+        text += "\n".join(line.strip() for line in t.splitlines() if line.strip()) + "\n"
     return hashlib.sha256(text.encode()).hexdigest()[:16]
 
 
@@ -78,7 +80,7 @@ def load_traffic(path=TRAFFIC_FILE, layout=None):
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kf_solve_hip_sha256_16") != source_hash(SOLVER_SRC):
+    if t.get("solver_source_sha256_16") != source_hash(*SOLVER_SRCS):
         return None
     if layout is not None and t.get("launch_layout") != layout:
         return None

@@ -108,7 +108,7 @@ struct Tiling {
 };
 
 constexpr int NV_MAX = 3;            // values reduced per synchronisation
-constexpr int PART_REPLICAS = 4;     // copies of each published partial (readers spread over them)
+constexpr int PART_REPLICAS = 8;     // copies of each published partial (readers spread over them)
 constexpr int MAX_TEAM = 256;        // workgroups per keyframe team
 constexpr int CHUNK = 256;           // pixels per compaction chunk
 #define KF_BATCH_MAX KF_BATCH_MAX_MEMBERS
