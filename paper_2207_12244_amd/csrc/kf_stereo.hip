@@ -2,11 +2,14 @@
 // two steps, variance of eq. (semi), inverse-depth Gaussian filter.
 //
 // Work mapping: a group of G lanes of one wavefront (lanes_per_pixel) handles
-// one textured keyframe pixel; lane l of the group evaluates samples k = l,
-// l + G, ... The keyframe pattern (5 or 25 values) is evaluated once per pixel
-// and handed to every lane of the group by cross-lane broadcasts; the argmin
-// over the N_s SSDs is a butterfly of cross-lane shuffles inside the group
-// with ties resolved to the smaller k. No LDS, no barriers.
+// one textured keyframe pixel; lane l of the group evaluates S = N_s / G
+// samples: k = l S, ..., l S + S - 1 for the 5-point line pattern (consecutive
+// samples share four of their five points when the step is 1 px) and k = l,
+// l + G, ... for the 5 x 5 patch. The keyframe pattern (5 or 25 values) is
+// evaluated once per pixel and handed to every lane of the group by cross-lane
+// broadcasts; the argmin over the N_s SSDs is a butterfly of cross-lane
+// shuffles inside the group with ties resolved to the smaller k. No LDS, no
+// barriers.
 #include "kf_internal.h"
 
 namespace kf {
@@ -21,7 +24,7 @@ constexpr int ST_WAVES = ST_THREADS / 64;
 // which every lane of the group repeats, is spread over several pixels per
 // wavefront; at least 32 lanes for the 25-point pattern, so that each of its
 // points is evaluated by one lane and broadcast. Any split gives the same
-// result (the argmin is a lexicographic (SSD, k) minimum).
+// argmin (a lexicographic (SSD, k) minimum) of the same SSDs.
 constexpr int lanes_per_pixel(int pat, int ns) {
   int g = ns / 4 < 1 ? 1 : (ns / 4 > 64 ? 64 : ns / 4);
   if (pat == KF_PAT_SQ5X5 && g < 32) g = ns < 32 ? ns : 32;
@@ -277,18 +280,45 @@ __device__ inline bool stereo_pixel(const StereoArgs& a, int idx, bool active, i
     for (int j = 0; j < P; ++j) pat[j] = active ? kf_point<T, TI, PAT>(i0, W, H, u, v, g, j) : (T)0;
   }
 
-  // SSD of this lane's samples
+  // SSD of this lane's samples. LINE5 lanes take S consecutive samples
+  // (k = gl S + s): with a 1-px step, point j + 1 of sample k is point j of
+  // sample k + 1, so the lane evaluates S + 4 bilinear points instead of 5 S.
+  // SQ5X5 lanes take every G-th sample.
+  constexpr bool CONSEC = PAT == KF_PAT_LINE5;
   T ssd[S];
   T best = INF;
   int bestk = 0x7fffffff;
+  const bool shared_pts = CONSEC && g.ok && g.h == (T)1;
+  T bv[S + 4];
+  bool bin[S + 4];
+  if (CONSEC) {
+    T qx, qy, qr;
+    sample_pos<T, NS>(g, a.fc, gl * S, qx, qy, qr);
+#pragma unroll
+    for (int t = 0; t < S + 4; ++t) {
+      const T tu = qx + (T)(t - 2) * g.lx, tv = qy + (T)(t - 2) * g.ly;
+      bin[t] = shared_pts && inside<T>(tu, tv, W, H);
+      bv[t] = bin[t] ? bilin_u8<T>(gp(a.i1s), st, W, H, tu, tv) : (T)0;
+    }
+  }
 #pragma unroll
   for (int s = 0; s < S; ++s) {
-    const int k = gl + G * s;
+    const int k = CONSEC ? gl * S + s : gl + G * s;
     T px, py, rk;
     sample_pos<T, NS>(g, a.fc, k, px, py, rk);
     bool ok = g.ok && isfinite((double)rk) && rk >= (T)a.fc.rho_min && rk <= (T)a.fc.rho_max;
     T acc = (T)0;
-    if (PAT == KF_PAT_LINE5) {
+    if (PAT == KF_PAT_LINE5 && shared_pts) {
+#pragma unroll
+      for (int j = 0; j < 5; ++j) ok = ok && bin[s + j];
+      if (ok) {
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+          const T e = bv[s + j] - pat[j];
+          acc += e * e;
+        }
+      }
+    } else if (PAT == KF_PAT_LINE5) {
 #pragma unroll
       for (int j = 0; j < 5; ++j) {
         const T jj = (T)(j - 2);
@@ -358,15 +388,16 @@ __device__ inline bool stereo_pixel(const StereoArgs& a, int idx, bool active, i
     const int base = grp * G;
     T vm = INF, vp = INF;
     // every lane reads its own slot value for the owner's sample index
-    const int slot_m = km >= 0 ? km / G : 0, slot_p = kp < NS ? kp / G : 0;
+    const int slot_m = km >= 0 ? (CONSEC ? km % S : km / G) : 0;
+    const int slot_p = kp < NS ? (CONSEC ? kp % S : kp / G) : 0;
     T mine_m = ssd[0], mine_p = ssd[0];
 #pragma unroll
     for (int s = 1; s < S; ++s) {
       if (slot_m == s) mine_m = ssd[s];
       if (slot_p == s) mine_p = ssd[s];
     }
-    vm = shfl_t(mine_m, base + (km >= 0 ? km % G : 0));
-    vp = shfl_t(mine_p, base + (kp < NS ? kp % G : 0));
+    vm = shfl_t(mine_m, base + (km >= 0 ? (CONSEC ? km / S : km % G) : 0));
+    vp = shfl_t(mine_p, base + (kp < NS ? (CONSEC ? kp / S : kp % G) : 0));
     s_m = km >= 0 ? vm : INF;
     s_p = kp < NS ? vp : INF;
   }
