@@ -19,14 +19,17 @@ namespace {
 constexpr int ST_THREADS = 256;
 constexpr int ST_WAVES = ST_THREADS / 64;
 
-// Lanes of a wavefront that share one textured pixel: about 4 samples per
-// lane, so that the per-pixel work (geometry, argmin, sub-pixel step, filter),
-// which every lane of the group repeats, is spread over several pixels per
-// wavefront; at least 32 lanes for the 25-point pattern, so that each of its
-// points is evaluated by one lane and broadcast. Any split gives the same
-// argmin (a lexicographic (SSD, k) minimum) of the same SSDs.
+// Lanes of a wavefront that share one textured pixel: 16 samples per lane for
+// the 5-point line pattern (whose consecutive samples share points) and about
+// 4 for the 25-point patch, so that the per-pixel work (geometry, argmin,
+// sub-pixel step, filter), which every lane of the group repeats, is spread
+// over several pixels per wavefront; at least 32 lanes for the 25-point
+// pattern, so that each of its points is evaluated by one lane and broadcast.
+// Any split gives the same argmin (a lexicographic (SSD, k) minimum) of the
+// same SSDs.
 constexpr int lanes_per_pixel(int pat, int ns) {
-  int g = ns / 4 < 1 ? 1 : (ns / 4 > 64 ? 64 : ns / 4);
+  const int per = pat == KF_PAT_LINE5 ? 16 : 4;
+  int g = ns / per < 1 ? 1 : (ns / per > 64 ? 64 : ns / per);
   if (pat == KF_PAT_SQ5X5 && g < 32) g = ns < 32 ? ns : 32;
   return g;
 }
