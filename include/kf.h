@@ -127,7 +127,11 @@ void kf_config_default(kf_config* cfg, int32_t width, int32_t height);
 /* Device bytes a context with this configuration needs; 0 if cfg is invalid. */
 size_t kf_workspace_bytes(const kf_config* cfg);
 
-/* Validates cfg and binds the workspace. No device work. *out = NULL on error. */
+/* Validates cfg and binds the workspace. No device work. *out = NULL on error.
+   The paper defines no such call (it runs one keyframe at a time); the context
+   is this library's unit of resident state. cfg and the workspace are the
+   caller's; the context keeps a copy of cfg and a pointer to the workspace,
+   which must outlive it. */
 kf_status kf_create(const kf_config* cfg, kf_ctx** out);
 
 /* Frees the host-side context (not the workspace). NULL is allowed. */
@@ -156,12 +160,24 @@ kf_status kf_stereo_update(kf_ctx* ctx, const uint8_t* image1, const double T_wc
 /* Optimisation only (Sec. II-C): n_gn Gauss-Newton iterations from the current state. */
 kf_status kf_solve(kf_ctx* ctx);
 
-/* The per-frame update: kf_stereo_update followed by kf_solve. */
+/* The per-frame update of Sec. II: the semi-dense update of Sec. II-B (epipolar
+   search, interpolation between two steps, variance of eq. (semi), inverse-depth
+   filter) followed by the optimisation of Sec. II-C (c_semi + c_net + c_grad with
+   Huber terms, n_gn Gauss-Newton iterations alternating depth and scale, warm
+   started from the current state). Same as kf_stereo_update then kf_solve.
+   image1: device uint8, H x W, row-major, owned by the caller, alive until the
+   stream has passed this call; T_wc1: host double[16], copied. Returns
+   KF_ERR_STATE before kf_set_prior, KF_ERR_ARG for a NULL image or a pose that is
+   not finite or has a last row other than 0 0 0 1. */
 kf_status kf_fuse_frame(kf_ctx* ctx, const uint8_t* image1, const double T_wc1[16]);
 
-/* Writes depth = exp(x) (device, H x W, map element type) and, if var_out is not
-   NULL, the inverse-depth filter variance (0 where no estimate); *scale_out (host,
-   nullable) receives s. Synchronises the stream; returns a pending device error. */
+/* The result of Sec. II-C: the keyframe depth map d = exp(x) (x = ln d is the
+   optimised log-depth) and the scale s = exp(tau) of the semi-dense term.
+   Writes depth (device, H x W, map element type, caller-owned) and, if var_out is
+   not NULL, the inverse-depth filter variance of Sec. II-B (0 where no estimate);
+   *scale_out (host, nullable) receives s. Synchronises the stream; returns a
+   pending device error (KF_ERR_INPUT, KF_ERR_TIMEOUT) or KF_ERR_STATE before
+   kf_set_prior. */
 kf_status kf_read_depth(kf_ctx* ctx, void* depth_out, void* var_out, double* scale_out);
 
 /* Statistics of the last stereo update and solve (host struct). Synchronises. */

@@ -20,15 +20,16 @@ The oracle is written for a reader holding the paper, in the paper's order:
   and scale; plus a converged mode giving the unique minimiser.
 * ``pipeline``  - keyframe state: set prior, fuse frame, read depth.
 
-Every reading taken where the paper is silent or ambiguous is listed in
-``readings.READINGS`` and repeated in the design notes.
+Where the paper is silent or ambiguous a reading is taken (R1 ... R21); each
+function names the readings it follows, and the design notes list them all.
 
 Pins: every function here is checked by ``tests/test_oracle_*.py`` against
-closed forms, invariants, brute force or independent library routines; no
-function is "parity unpinned" except where a test's docstring says so.
+closed forms, invariants, brute force or independent library routines (the
+texture gate, the bilinear sampler at fractional points and the direction of
+the sub-pixel step included); no function is "parity unpinned".
 """
 
-from . import geometry, stereo, fusion, pipeline, readings  # noqa: F401
+from . import geometry, stereo, fusion, pipeline  # noqa: F401
 from .stereo import StereoParams  # noqa: F401
 from .fusion import SolverParams, PriorMaps, SemiMeasurements  # noqa: F401
 from .pipeline import OracleKeyframe  # noqa: F401

@@ -384,14 +384,22 @@ class Keyframe:
                      self._map(grad_x_var, "grad_x_var"), self._map(grad_y, "grad_y"),
                      self._map(grad_y_var, "grad_y_var"), T_wc0)
 
+    def _hold(self, image1):
+        # the library reads image1 when the stream reaches the call: keep the
+        # caching allocator from handing its memory out before then
+        if image1.device.type == "cuda":
+            image1.record_stream(self.stream)
+
     def stereo_update(self, image1, T_wc1):
         kf_stereo_update(self.ctx, self._img(image1, "image1"), T_wc1)
+        self._hold(image1)
 
     def solve(self):
         kf_solve(self.ctx)
 
     def fuse_frame(self, image1, T_wc1):
         kf_fuse_frame(self.ctx, self._img(image1, "image1"), T_wc1)
+        self._hold(image1)
 
     def read_depth(self, with_var: bool = False):
         torch = _torch()

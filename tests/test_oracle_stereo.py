@@ -262,3 +262,97 @@ def test_float32_decisions_agree_with_float64_outside_ties(case_c0):
     assert clear.mean() > 0.95
     assert np.array_equal(a.k_best[ok][clear], b.k_best[ok][clear])
     assert np.mean(a.status == b.status) > 0.999
+
+
+# ------------------------------------------------------------------ pins of the texture gate,
+# the bilinear sampler at fractional positions and the direction of the sub-pixel step
+
+def _gate_image(a, b, H=16, W=20):
+    """uint8 image whose central differences are exactly I[u+1]-I[u-1] = a and I[v+1]-I[v-1] = b
+    everywhere inside: I = floor(a u / 2) + floor(b v / 2) (steps alternate for odd a, b)."""
+    uu, vv = np.meshgrid(np.arange(W), np.arange(H))
+    return (np.floor(a * uu / 2.0) + np.floor(b * vv / 2.0)).astype(np.uint8)
+
+
+def test_texture_gate_threshold_is_on_the_halved_gradient_norm():
+    """R1 (Sec. II-B, 'sufficient texture'): |((I[u+1]-I[u-1])/2, (I[v+1]-I[v-1])/2)| >= 6.
+
+    Cases and the mistakes each one catches:
+    - ramp I = 6u: halved difference exactly 6 -> textured (a strict '>' gate fails);
+    - ramp with steps 5, 6, 5, ...: halved difference 5.5 -> not textured (a gate on the
+      un-halved difference 11 fails, and so does a gate on |grad|^2 >= 6, since 5.5^2 >= 6);
+    - a = 8, b = 9: (4, 4.5), norm sqrt(36.25) -> textured (a max-norm or x-only gate fails);
+    - a = 7, b = 9: (3.5, 4.5), norm sqrt(32.5) -> not textured (an L1 gate, 8 >= 6, fails).
+    """
+    inner = (slice(2, -2), slice(2, -2))
+    for a, b, textured in ((12, 0, True), (11, 0, False), (8, 9, True), (7, 9, False), (0, 12, True),
+                           (0, 11, False)):
+        I = _gate_image(a, b)
+        m = stereo.texture_mask(I, 6.0, 2)
+        assert np.all(m[inner] == textured), (a, b)
+    # exactly on the gate in x alone: I = 6u has I[u+1] - I[u-1] = 12
+    assert np.array_equal(_gate_image(12, 0), (6 * np.tile(np.arange(20), (16, 1))).astype(np.uint8))
+
+
+def test_texture_gate_border_is_two_pixels():
+    """R1: a border of 2 px is never searched; the third row / column is (a border of 1 or 3 fails)."""
+    I = _gate_image(20, 20, H=12, W=14)
+    m = stereo.texture_mask(I, 6.0, 2)
+    H, W = I.shape
+    expect = np.zeros((H, W), bool)
+    expect[2:H - 2, 2:W - 2] = True
+    assert np.array_equal(m, expect)
+
+
+def test_bilinear_reproduces_bilinear_functions_at_fractional_points():
+    """Bilinear interpolation is exact on I(u, v) = a + b u + c v + d u v, at any fractional point,
+    including points in the last cell (u in [W-2, W-1], v in [H-2, H-1]) and on its far edges,
+    where the cell origin is clamped to W-2 / H-2. Swapping the u and v fractions (f <-> g), the
+    weights of I10 and I01, or dropping the clamp all fail."""
+    rng = np.random.default_rng(11)
+    H, W = 9, 13
+    uu, vv = np.meshgrid(np.arange(W, dtype=np.float64), np.arange(H, dtype=np.float64))
+    for _ in range(5):
+        a, b, c, d = rng.uniform(-3, 3, 4)
+        img = a + b * uu + c * vv + d * uu * vv
+        u = np.concatenate([rng.uniform(0, W - 1, 400), rng.uniform(W - 2, W - 1, 50), [W - 1.0, 0.0, W - 1.0]])
+        v = np.concatenate([rng.uniform(0, H - 1, 400), rng.uniform(H - 2, H - 1, 50), [H - 1.0, H - 1.0, 0.0]])
+        got = stereo.bilinear(img, u, v)
+        assert np.allclose(got, a + b * u + c * v + d * u * v, rtol=0, atol=1e-12)
+    # an image that is linear in u only must not depend on the v fraction (catches f <-> g)
+    img = np.tile(np.arange(W, dtype=np.float64) * 5.0, (H, 1))
+    assert np.allclose(stereo.bilinear(img, np.array([3.25]), np.array([4.75])), [16.25], atol=1e-13)
+
+
+@pytest.mark.parametrize("pattern,P", [("line5", 5), ("sq5x5", 25)])
+def test_subpixel_step_direction_on_an_asymmetric_ramp(pattern, P):
+    """R6 (Sec. II-B, interpolation between two steps), asymmetric case.
+
+    I1(u') = I0(u' + 6.25) on a ramp of slope 8: sample k sits at disparity k + 1, so every
+    pattern point has e_k = 8 (6.25 - (k + 1)) = 42 - 8 k: e_5 = 2, e_6 = -6, e_4 = 10.
+    Then k* = 5, n* = 6 (SSD 36 P < 100 P), de = -8, lambda* = -(2)(-8) / 64 = 1/4 exactly,
+    d* = d_a + (d_b - d_a) / 4 with d_a = 8/6, d_b = 8/7 (linear in depth), and
+    sigma_d^2 = (d_b - d_a)^2 / (64 P).
+    Mistakes caught: interpolating from n* towards k* (lambda 3/4 from d_b), the opposite sign of
+    lambda (clipped to 0), interpolating in inverse depth, taking the higher-SSD neighbour.
+    """
+    K, T0, T1, I0, _ = _stereo_pair(ramp=True, W=32)
+    H, W = I0.shape
+    uu = np.tile(np.arange(W), (H, 1))
+    I1 = (8 * uu + 50).clip(0, 255).astype(np.uint8)            # I1(u') = I0(u' + 6.25)
+    sp = StereoParams(n_samples=16, pattern=pattern, d_near=0.5, d_far=8.0)
+    mask = stereo.texture_mask(I0, sp.grad_gate)
+    z = np.zeros((H, W))
+    res = stereo.epipolar_search(I0, I1, K, T0, T1, z, z, np.zeros((H, W), bool), mask, sp)
+    u = res.pix % W
+    sel = (u >= 10) & (u <= 28)
+    assert sel.sum() > 20
+    assert np.all(res.status[sel] == UPDATED)
+    rows = np.flatnonzero(sel)
+    assert np.all(res.ssd[rows, 5] == 4.0 * P) and np.all(res.ssd[rows, 6] == 36.0 * P)
+    assert np.all(res.ssd[rows, 4] == 100.0 * P)
+    assert np.all(res.k_best[sel] == 5) and np.all(res.k_nbr[sel] == 6)
+    assert np.all(res.lam[sel] == 0.25)
+    d_a, d_b = 8.0 / 6.0, 8.0 / 7.0
+    assert np.allclose(res.d_star[sel], d_a + 0.25 * (d_b - d_a), rtol=1e-15, atol=0)
+    assert np.allclose(res.var_d[sel], (d_b - d_a) ** 2 / (64.0 * P), rtol=1e-13, atol=0)
