@@ -87,37 +87,85 @@ def load_traffic(path=TRAFFIC_FILE, layout=None):
     return t.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(case, wl):
-    """The FP64 oracle, as it stands, on frame 1 of the same sequence (stereo on
-    every textured pixel + 10 x 20 PCG fusion), timed on the host."""
-    from oracle import OracleKeyframe, SolverParams, StereoParams
-    ok = OracleKeyframe(case.K, case.W, case.H, StereoParams(n_samples=wl["n_samples"], pattern=wl["pattern"]),
-                        SolverParams(n_gn=wl["n_gn"], n_cg=wl["n_cg"], linear_solver="pcg"))
-    ok.set_prior(case.image0, *case.priors.maps(), case.T_wc0)
-    w0, c0 = time.perf_counter(), time.process_time()
-    ok.fuse_frame(case.images[0], case.poses[0])
-    w1, c1 = time.perf_counter(), time.process_time()
-    wall = w1 - w0
-    cores = max(1, int(round((c1 - c0) / wall)))
-    return {"value": round(case.W * case.H / wall / 1e6, 6), "unit": "Mpixel/s", "cores": cores, "kind": "oracle",
-            "sample": f"1 frame (frame 1 of the 30-frame sequence) of the same {case.W}x{case.H} workload, "
-                      f"{wall:.1f} s wall on the host", "seconds": round(wall, 3)}, ok
+def host_cpu():
+    """Logical CPUs of the host and its CPU model (from /proc/cpuinfo)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"host_cpus": os.cpu_count(), "cpu_model": model}
 
 
-def accuracy_vs_oracle(ok, case, wl, torch):
-    """Depth of the GPU form after the same first frame, against the oracle's."""
+def oracle_pool(workers):
+    """Processes for the oracle's per-pixel search (spawned: they never touch the GPU)."""
+    import concurrent.futures
+    import multiprocessing
+    return concurrent.futures.ProcessPoolExecutor(workers, mp_context=multiprocessing.get_context("spawn"))
+
+
+def gpu_states_per_frame(case, wl, torch):
+    """The precision form run once more on one stream (untimed): log-depth x and
+    the match indices after every frame, for the comparison with the oracle."""
     from paper_2207_12244_amd.kf import Keyframe
     dev = lambda x, dt: torch.as_tensor(np.ascontiguousarray(x), dtype=dt, device="cuda")
     kf = Keyframe(case.W, case.H, precision=wl["precision"], pattern=wl["pattern"], n_samples=wl["n_samples"],
                   n_gn=wl["n_gn"], n_cg=wl["n_cg"], K=case.K)
     kf.set_prior(dev(case.image0, torch.uint8), *[dev(m, torch.float32) for m in case.priors.maps()], case.T_wc0)
-    kf.fuse_frame(dev(case.images[0], torch.uint8), case.poses[0])
-    d, s = kf.read_depth()
-    d_o, s_o = ok.read_depth()
-    rel = np.abs(d.cpu().numpy().astype(np.float64) / d_o - 1.0)
-    return {"depth_rel_err_max": float(f"{rel.max():.4g}"), "depth_rel_err_rms": float(f"{np.sqrt(np.mean(rel ** 2)):.4g}"),
-            "scale_rel_err": float(f"{abs(s / s_o - 1.0):.4g}"),
-            "against": "FP64 oracle, same first frame, iteration-matched 10 x 20 Jacobi PCG"}
+    out = []
+    for f in range(len(case.images)):
+        kf.fuse_frame(dev(case.images[f], torch.uint8), case.poses[f])
+        st = kf.export_state()
+        out.append((st["x"].cpu().numpy().astype(np.float64), st["match"].cpu().numpy(), st["tau"]))
+    kf.close()
+    return out
+
+
+def cpu_baseline_and_accuracy(case, wl, gpu_states, workers):
+    """The FP64 oracle, as it stands, fused over the whole 30-frame sequence of
+    one step (stereo over the textured pixels in row blocks on a process pool,
+    10 x 20 Jacobi PCG fusion in this process), timed on the host; after every
+    frame its depth is compared with the GPU form's."""
+    from oracle import OracleKeyframe, SolverParams, StereoParams
+    with oracle_pool(workers) as pool:
+        ok = OracleKeyframe(case.K, case.W, case.H, StereoParams(n_samples=wl["n_samples"], pattern=wl["pattern"]),
+                            SolverParams(n_gn=wl["n_gn"], n_cg=wl["n_cg"], linear_solver="pcg"), pool=pool,
+                            n_blocks=2 * workers)
+        ok.set_prior(case.image0, *case.priors.maps(), case.T_wc0)
+        pool.submit(int, 0).result()   # workers up before the clock starts
+        per_frame = []
+        wall = 0.0
+        for f in range(len(case.images)):
+            w0 = time.perf_counter()
+            rep = ok.fuse_frame(case.images[f], case.poses[f])
+            wall += time.perf_counter() - w0
+            x_g, match_g, tau_g = gpu_states[f]
+            rel = np.abs(np.exp(x_g - ok.x) - 1.0)
+            mism = int(np.count_nonzero(match_g.ravel()[rep.search.pix] != rep.search.k_best))
+            per_frame.append({"frame": f + 1, "depth_rel_err_max": float(f"{rel.max():.4g}"),
+                              "depth_rel_err_rms": float(f"{np.sqrt(np.mean(rel ** 2)):.4g}"),
+                              "scale_rel_err": float(f"{abs(np.exp(tau_g - ok.tau) - 1.0):.4g}"),
+                              "index_mismatch_rate": float(f"{mism / max(1, rep.search.pix.size):.4g}")})
+            print(f"# oracle frame {f + 1}: {per_frame[-1]}", file=sys.stderr, flush=True)
+    nF = len(case.images)
+    base = {"value": round(nF * case.W * case.H / wall / 1e6, 6), "unit": "Mpixel/s", "cores": workers + 1,
+            "kind": "oracle",
+            "sample": f"the whole {nF}-frame sequence of one step ({case.W}x{case.H}, stereo on a {workers}-process "
+                      f"pool, PCG fusion in the main process), {wall:.1f} s wall on the host",
+            "seconds": round(wall, 3), **host_cpu()}
+    last = per_frame[-1]
+    acc = {"after_frame": nF, "depth_rel_err_max": last["depth_rel_err_max"],
+           "depth_rel_err_rms": last["depth_rel_err_rms"], "scale_rel_err": last["scale_rel_err"],
+           "worst_frame_rms": max(p["depth_rel_err_rms"] for p in per_frame),
+           "worst_frame_index_mismatch_rate": max(p["index_mismatch_rate"] for p in per_frame),
+           "against": "FP64 oracle run on its own over the same sequence, iteration-matched 10 x 20 Jacobi PCG; "
+                      "the two drift apart through near-tie stereo decisions",
+           "per_frame": per_frame}
+    return base, acc
 
 
 def _gen_batched_case(i):
@@ -157,11 +205,12 @@ def cpu_baseline_batched(cases, wl):
         wall += time.perf_counter() - w0
         cpu += time.process_time() - c0
         px += W * H
-    cores = max(1, int(round(cpu / wall)))
+    threads = max(1, int(round(cpu / wall)))
     sizes = ", ".join(f"{W}x{H}" for W, H in sorted(picked))
-    return {"value": round(px / wall / 1e6, 6), "unit": "Mpixel/s", "cores": cores, "kind": "oracle",
-            "sample": f"one keyframe of each size in the batch ({sizes}) fused with its frame, {wall:.1f} s wall",
-            "seconds": round(wall, 3)}
+    return {"value": round(px / wall / 1e6, 6), "unit": "Mpixel/s", "cores": threads, "kind": "oracle",
+            "sample": f"one keyframe of each size in the batch ({sizes}) fused with its frame in one process "
+                      f"(cores = CPU time / wall: numpy's threads), {wall:.1f} s wall",
+            "seconds": round(wall, 3), **host_cpu()}
 
 
 def run_batched(a, torch, cases):
@@ -230,14 +279,70 @@ def run_batched(a, torch, cases):
                        "p99": round(float(np.percentile(lat_ms, 99)), 4)},
         "stage_ms_per_step": {"stereo": round(float(np.mean(stereo_ms)), 4),
                               "solve": round(float(np.mean(solve_ms)), 4)},
-        "roofline": {"kernel": "k_solve_batch", "bound": "hbm", "achieved": round(achieved, 2),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": load_traffic(BATCH_TRAFFIC_FILE, batch.layout()), "algorithmic_bytes_per_launch": bpl,
-                     "avg_launch_ms": round(solve_avg_s * 1000.0, 4)},
+        "roofline": roofline_entry("k_solve_batch", bpl, solve_avg_s, load_traffic(BATCH_TRAFFIC_FILE, batch.layout())),
     }
+    lay = batch.layout()
+    out["roofline"]["dependent_syncs_longest_queue"] = lay["max_queue"] * members[0].stats().team_syncs
+    batch.close()
+    out["plain_same_workload"] = run_plain_batched(a, torch, cases, wl, imgs, poses, out["value"])
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_batched(cases, wl)
-    batch.close()
+    return out
+
+
+def run_plain_batched(a, torch, cases, wl, imgs, poses, batched_value):
+    """The plain form on the batched workload: one context per keyframe with the
+    plain form's own (latency-optimal) tiling, a step = one kf_fuse_frame per
+    keyframe on one stream. Results equal the batched form's bit for bit when
+    the tilings match; here each keyframe keeps its own best tiling."""
+    from paper_2207_12244_amd.kf import Keyframe
+    dev = lambda x, dt: torch.as_tensor(np.ascontiguousarray(x), dtype=dt, device="cuda")
+    plain = []
+    for c in cases:
+        kf = Keyframe(c.W, c.H, K=c.K, precision=wl["precision"], pattern=wl["pattern"], n_samples=wl["n_samples"],
+                      n_gn=wl["n_gn"], n_cg=wl["n_cg"])
+        kf.set_prior(dev(c.image0, torch.uint8), *[dev(m, torch.float32) for m in c.priors.maps()], c.T_wc0)
+        plain.append(kf)
+
+    def pstep():
+        for kf, im, po in zip(plain, imgs, poses):
+            kf.fuse_frame(im, po)
+
+    for _ in range(max(1, a.warmup)):
+        pstep()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.batched_steps):
+        pstep()
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    for kf in plain:
+        kf.close()
+    px = sum(c.W * c.H for c in cases)
+    value = px * a.batched_steps / total / 1e6
+    return {"value": round(value, 3), "unit": "Mpixel/s", "ms_per_step": round(1000.0 * total / a.batched_steps, 3),
+            "batched_speedup": round(batched_value / value, 3),
+            "mode": f"{len(cases)} kf_fuse_frame calls per step on one stream, each keyframe with its own "
+                    "latency-optimal tiling; same frames, poses and settings as the batched form"}
+
+
+def roofline_entry(kernel, bpl, launch_s, traffic, sync=None):
+    """The solver's roofline figures: algorithmic sweep bytes per launch / launch
+    time against HBM peak (achieved, frac), the HBM bytes rocprofv3 counted per
+    launch (traffic) and the rate they give, and the team-synchronisation floor.
+    The vectors of a tile stay in registers and LDS, so the counted traffic is
+    a small part of the sweeps: the launch is bound by the latency of its
+    dependent team synchronisations, not by HBM."""
+    achieved = bpl / launch_s / 1e9
+    out = {"kernel": kernel, "bound": "latency", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+           "achieved_basis": "algorithmic sweep bytes (23 + 9 n_cg) x 4 B per pixel per GN iteration / launch time",
+           "algorithmic_bytes_per_launch": bpl, "avg_launch_ms": round(launch_s * 1000.0, 4)}
+    if traffic:
+        out["counted_gbs"] = round(traffic / launch_s / 1e9, 2)
+        out["counted_frac"] = round(traffic / launch_s / 1e9 / HBM_PEAK_GBS, 4)
+    if sync is not None:
+        out["sync"] = sync
     return out
 
 
@@ -313,7 +418,57 @@ def run_serving(a, torch, streams):
                       "shape_policy": {"threads": pol["threads"], "px_per_thread_cap": pol["ppt"]} if pol
                       else "latency-optimal per size"}}
     srv.close()
+    out["plain_capacity"] = run_plain_serving(torch, streams, w, out["capacity"]["mpx_s"])
     return out
+
+
+def run_plain_serving(torch, streams, w, served_capacity):
+    """The plain form on the serving requests at full rate: one context per
+    stream, every request in arrival order as one kf_set_prior / kf_fuse_frame
+    call on one stream, inputs already on the device."""
+    from paper_2207_12244_amd.kf import Keyframe
+    dev = lambda x, dt: torch.as_tensor(np.ascontiguousarray(x), dtype=dt, device="cuda")
+    kfs = [Keyframe(c.W, c.H, K=c.K, precision=w["precision"], pattern=w["pattern"], n_samples=w["n_samples"],
+                    n_gn=w["n_gn"], n_cg=w["n_cg"]) for c, _ in streams]
+    cache = {}
+
+    def up(arr, dt):
+        key = id(arr)
+        if key not in cache:
+            cache[key] = (arr, dev(arr, dt))
+        return cache[key][1]
+
+    reqs = sorted(((r["t"], sid, i) for sid, (_, rs) in enumerate(streams) for i, r in enumerate(rs)))
+    calls = []
+    for _, sid, i in reqs:
+        r = streams[sid][1][i]
+        if r["kind"] == "keyframe":
+            calls.append((sid, up(r["image"], torch.uint8), [up(m, torch.float32) for m in r["priors"]], r["pose"]))
+        else:
+            calls.append((sid, up(r["image"], torch.uint8), None, r["pose"]))
+
+    def run():
+        px = 0
+        for sid, img, pri, pose in calls:
+            if pri is not None:
+                kfs[sid].set_prior(img, *pri, pose)
+            else:
+                kfs[sid].fuse_frame(img, pose)
+                px += kfs[sid].W * kfs[sid].H
+        return px
+
+    run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    px = run()
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    for kf in kfs:
+        kf.close()
+    value = px / total / 1e6
+    return {"mpx_s": round(value, 3), "served_capacity_speedup": round(served_capacity / value, 3),
+            "mode": "every request of the serving workload in arrival order as one plain call on one stream, "
+                    "inputs resident (the served figure includes its host-to-device copies)"}
 
 
 def run_headline(a, torch):
@@ -376,18 +531,19 @@ def run_headline(a, torch):
     # one stream (one frame in flight): per-frame latency, stage times and the
     # solver's launch duration; then the pipelined context for the throughput
     kf, total1, stereo_ms, solve_ms, lat_ms = timed(False)
-    kfp, total, _, _, lat_p = timed(True)
+    solver_layout = kf.solver_layout()
+    syncs = kf.stats().team_syncs
+    sync = sync_floor(kf, torch, syncs, float(np.mean(solve_ms)))
     kf.close()
-    kf = kfp
+    kf, total, _, _, lat_p = timed(True)
     st = kf.stats()
+    kf.close()
     ms_per_step = 1000.0 * total / a.steps
     px = nF * case.W * case.H
     value = px / (ms_per_step / 1000.0) / 1e6
     N = case.W * case.H
     bpl = solver_bytes_per_frame(N, wl["n_gn"], wl["n_cg"])
     solve_avg_s = float(np.mean(solve_ms)) / 1000.0
-    achieved = bpl / solve_avg_s / 1e9
-    traffic = load_traffic(TRAFFIC_FILE, kf.solver_layout())
     out = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -402,38 +558,60 @@ def run_headline(a, torch):
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"{case.W}x{case.H} keyframe + {nF}-frame sequence, precision form (bf16 keyframe "
-                        f"image/patches, f32 maps and arithmetic, f64 CG dots), N_s={wl['n_samples']}, 5x5 patch, "
-                        f"{wl['n_gn']} GN x {wl['n_cg']} PCG per frame",
+            "workload": f"{case.W}x{case.H} keyframe + {nF}-frame sequence, precision form (keyframe image stored "
+                        f"as bf16, which is exact for uint8 images: with the 5x5 patch at integer keyframe pixels "
+                        f"no value is rounded to bf16, so the form computes as F32; f32 maps and arithmetic; CG inner "
+                        f"products accumulated in f64 and exchanged between workgroups with a 2^-37 relative "
+                        f"rounding), N_s={wl['n_samples']}, 5x5 patch, {wl['n_gn']} GN x {wl['n_cg']} PCG per frame",
             "frames_per_step": nF, "width": case.W, "height": case.H, "seed": kfsynth.seed_for(wl["config"], 0),
-            "solver_layout": kf.solver_layout(), "pipeline_frames": 1,
+            "solver_layout": solver_layout, "pipeline_frames": 1,
             "solver_launch": "cooperative" if a.cooperative else "plain",
             "cg_variant": "pipelined" if a.cg_variant in ("auto", "pipelined") else "textbook",
         },
-        "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 4),
-                       "p99": round(float(np.percentile(lat_ms, 99)), 4),
-                       "mode": "one frame in flight: stereo start to solve end"},
-        "pipelined": {"note": "value is measured with pipeline_frames=1: the next frame's stereo overlaps the "
-                              "current solve (second stream, double-buffered filter state, same results), so a "
-                              "frame fed back to back completes ~2 solves after its stereo starts",
-                      "latency_ms": {"p50": round(float(np.percentile(lat_p, 50)), 4),
-                                     "p99": round(float(np.percentile(lat_p, 99)), 4)}},
+        "latency_ms": {"p50": round(float(np.percentile(lat_p, 50)), 4),
+                       "p99": round(float(np.percentile(lat_p, 99)), 4),
+                       "mode": "measured with the value (pipeline_frames=1, frames back to back): stereo start to "
+                               "solve end; a frame waits for the previous frame's solve"},
         "single_stream": {"value": round(px / (total1 / a.steps) / 1e6, 3),
-                          "ms_per_step": round(1000.0 * total1 / a.steps, 3)},
+                          "ms_per_step": round(1000.0 * total1 / a.steps, 3),
+                          "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 4),
+                                         "p99": round(float(np.percentile(lat_ms, 99)), 4),
+                                         "mode": "one frame in flight: stereo start to solve end"}},
         "stage_ms_per_frame": {"stereo": round(float(np.mean(stereo_ms)), 4),
                                "solve": round(float(np.mean(solve_ms)), 4)},
-        "frame_stats": {"textured": st.n_searched, "semi_valid": st.n_valid, "scale": round(st.scale, 6)},
-        "roofline": {"kernel": "k_solve", "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "algorithmic_bytes_per_launch": bpl,
-                     "avg_launch_ms": round(solve_avg_s * 1000.0, 4)},
+        "frame_stats": {"textured": st.n_searched, "semi_valid": st.n_valid, "scale": round(st.scale, 6),
+                        "team_syncs_per_solve": syncs},
+        "roofline": roofline_entry("k_solve", bpl, solve_avg_s, load_traffic(TRAFFIC_FILE, solver_layout), sync),
         "context": {"paper": "16 ms semi-dense + 33 ms optimisation per frame on i7-5820K + GTX 980, "
                              "resolution unstated (Table IV)"},
     }
     if not a.no_cpu_baseline:
-        out["cpu_baseline"], ok = cpu_baseline(case, wl)
-        out["accuracy"] = accuracy_vs_oracle(ok, case, wl, torch)
+        gpu_states = gpu_states_per_frame(case, wl, torch)
+        workers = max(1, min(8, os.cpu_count() or 1))
+        out["cpu_baseline"], out["accuracy"] = cpu_baseline_and_accuracy(case, wl, gpu_states, workers)
     return out
+
+
+def sync_floor(kf, torch, syncs, solve_ms, rounds=2000):
+    """Team-synchronisation floor of the solve: the probe launch (same team,
+    tiling and exchange as the solve, no arithmetic) timed with HIP events on
+    the context's stream; floor = synchronisations per solve x time per probe
+    round."""
+    kf.probe_sync(rounds, 2)
+    best = None
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(kf.stream)
+        kf.probe_sync(rounds, 2)
+        e1.record(kf.stream)
+        e1.synchronize()
+        us = e0.elapsed_time(e1) * 1000.0 / rounds
+        best = us if best is None else min(best, us)
+    floor_ms = syncs * best / 1000.0
+    return {"syncs_per_launch": syncs, "probe_us_per_sync": round(best, 4), "floor_ms": round(floor_ms, 4),
+            "frac": round(floor_ms / solve_ms, 4),
+            "probe": f"kf_probe_sync: {rounds} exchanges of 2 partials + the tile boundary, same team and tiling "
+                     "as the solve, no arithmetic; fastest of 3 launches"}
 
 
 def main(argv=None):

@@ -67,6 +67,17 @@ typedef enum {
   KF_BF16_F32 = 2   /* float maps and arithmetic; keyframe image and patch buffers bf16 */
 } kf_precision;
 
+/* The optimisation of Sec. II-C, or one of the two ablations of Sec. III. */
+typedef enum {
+  KF_VARIANT_FULL = 0,          /* c_semi + c_net + c_grad, alternating depth and scale (Sec. II-C) */
+  KF_VARIANT_NO_PAIRWISE = 1,   /* Table III: no gradient (pairwise) terms; each depth step is the
+                                   per-pixel weighted mean of the network and semi-dense log-depths */
+  KF_VARIANT_SCALE_POSTFIT = 2  /* Table II: a scale-ambiguous log-depth y from c_semi + c_grad alone
+                                   (scale held fixed), then the least-squares fit of the scale to the
+                                   network log-depth, tau = mean(mu - y) over all pixels, x = y + tau;
+                                   gradient variances must be finite */
+} kf_variant;
+
 /* Matching pattern of the epipolar search (Sec. II-B). */
 typedef enum {
   KF_PAT_LINE5 = 0, /* five points, 1 px apart, along the epipolar lines of both images */
@@ -100,6 +111,16 @@ typedef struct {
                                    is double-buffered, so the next frame's stereo update overlaps the
                                    current frame's solve (same results); 0: one stream. A context with
                                    1 cannot join a batch. */
+  int32_t variant;              /* kf_variant (default KF_VARIANT_FULL) */
+  double lambda_trans;          /* Sec. II keyframe rule: a frame whose camera centre is more than
+                                   lambda_trans (pose units) from the keyframe's asks for a new
+                                   keyframe; 0 disables the test */
+  int32_t lambda_inliers;       /* ... or whose semi-dense update produced fewer than lambda_inliers
+                                   measurements ("inliers"); 0 disables the test. A frame that asks
+                                   for a new keyframe updates the semi-dense filter but is not fused:
+                                   the depth map keeps its last fused state, and
+                                   kf_frame_stats.new_keyframe reports why (the caller creates the
+                                   new keyframe with kf_set_prior and the network's outputs) */
   double solver_timeout_ms;     /* longest a solver workgroup waits for its team before the whole
                                    team gives up and flags KF_ERR_TIMEOUT (0 = default 2000 ms).
                                    After a timeout the state is undefined: call kf_set_prior. */
@@ -116,7 +137,12 @@ typedef struct {
   int32_t cg_iterations;    /* PCG iterations of the last solve, summed over GN iterations */
   double scale;             /* s = exp(tau) after the last solve */
   double cg_rel_residual;   /* ||r|| / ||b|| at the end of the last PCG solve (tolerance mode) */
+  int32_t team_syncs;       /* team synchronisations of the last solver launch (or probe) */
+  int32_t new_keyframe;     /* KF_NEW_KEYFRAME_* bits of the last frame (0: it was fused) */
 } kf_frame_stats;
+
+#define KF_NEW_KEYFRAME_TRANSLATION 1   /* camera centre moved more than lambda_trans */
+#define KF_NEW_KEYFRAME_INLIERS 2       /* fewer than lambda_inliers semi-dense measurements */
 
 /* Fills *cfg with the defaults of the readings documented with the library:
    n_samples 32, LINE5, n_gn 10, n_cg 20, cg_rtol 0, cg_max 4000, huber 1.345,
@@ -154,6 +180,29 @@ kf_status kf_set_prior(kf_ctx* ctx, const uint8_t* image0,
                        const void* grad_y, const void* grad_y_var,
                        const double T_wc0[16]);
 
+/* kf_set_prior from the network's outputs at the network's own resolution
+   (Sec. II-A: the network's inputs and outputs are 256 x 192). The six maps are
+   net_width x net_height (device, map element type, >= 2 x 2), in kf_set_prior's
+   order. They are resampled to the keyframe size bilinearly, with pixel centres
+   aligned: keyframe pixel u samples the network map at (u + 1/2) net_width /
+   width - 1/2, clamped. The network's log-depth is normalised by the focal length
+   of the camera it was trained with, so the log-depth is shifted by
+   ln(fx net_width / width / focal_ref): focal_ref is that training focal length in
+   pixels at the network's resolution, and fx net_width / width is this camera's
+   at the same resolution. The gradients are per network pixel; they are
+   rescaled to keyframe pixels by net_width / width (x) and net_height / height
+   (y), and their variances by the squares. The log-depth variance is resampled
+   unchanged (the paper scales neither gradients nor uncertainties by the focal
+   length). The maps may be freed once the stream has passed the call.
+   KF_ERR_ARG for a NULL map, a network size outside [2, 8192] or a focal_ref
+   that is not finite and > 0. */
+kf_status kf_set_prior_network(kf_ctx* ctx, const uint8_t* image0,
+                               const void* logdepth, const void* logdepth_var,
+                               const void* grad_x, const void* grad_x_var,
+                               const void* grad_y, const void* grad_y_var,
+                               int32_t net_width, int32_t net_height, double focal_ref,
+                               const double T_wc0[16]);
+
 /* Semi-dense update only (Sec. II-B) with a new frame (device uint8 image, host pose). */
 kf_status kf_stereo_update(kf_ctx* ctx, const uint8_t* image1, const double T_wc1[16]);
 
@@ -182,6 +231,16 @@ kf_status kf_read_depth(kf_ctx* ctx, void* depth_out, void* var_out, double* sca
 
 /* Statistics of the last stereo update and solve (host struct). Synchronises. */
 kf_status kf_read_stats(kf_ctx* ctx, kf_frame_stats* out);
+
+/* Measurement aid, not part of the method: enqueues on cfg.stream one launch
+   of the solver's workgroup team (same tiling, workgroup size and exchange
+   words as kf_solve) that makes `rounds` team synchronisations of the kind one
+   pipelined PCG iteration makes (`nvalues` inner-product partials, 1..3, plus
+   the tile boundary of the stencil operand) and no arithmetic. The caller times
+   it (events on cfg.stream); time / rounds is the synchronisation latency that
+   bounds the solve. rounds in [1, 20000]. KF_ERR_STATE before kf_set_prior or
+   with pipeline_frames; the resident depth state is not touched. */
+kf_status kf_probe_sync(kf_ctx* ctx, int32_t rounds, int32_t nvalues);
 
 /* The internal stream the solves run on when cfg.pipeline_frames = 1 (NULL
    otherwise), for callers that time or order work against the solve. */

@@ -18,7 +18,10 @@ The oracle is written for a reader holding the paper, in the paper's order:
   term (Sec. II-C), its normal equations on the 5-point grid, a direct sparse
   solve, Jacobi-preconditioned CG, and Gauss-Newton alternating between depth
   and scale; plus a converged mode giving the unique minimiser.
-* ``pipeline``  - keyframe state: set prior, fuse frame, read depth.
+* ``pipeline``  - keyframe state: set prior, fuse frame, read depth; the
+  keyframe rule (Sec. II); the search of disjoint pixel blocks on a pool.
+* ``priors``    - the network's outputs at its own resolution resampled to the
+  keyframe, with the focal-length log-depth shift (Sec. II-A).
 
 Where the paper is silent or ambiguous a reading is taken (R1 ... R21); each
 function names the readings it follows, and the design notes list them all.

@@ -20,6 +20,17 @@ Solvers:
   solve or Jacobi PCG with a given iteration count / tolerance (reading R14).
 * ``minimiser``: the unique minimiser (x*, tau*) by IRLS on the joint system
   (x and tau together) until the update stops, then exact Newton polishing.
+
+The two ablations of Sec. III are variants of ``gauss_newton``
+(``SolverParams.variant``):
+* "no_pairwise" (Table III): the cost without c_grad. A is then diagonal and
+  each Gauss-Newton x-step is the per-pixel weighted mean of the network and
+  semi-dense log-depths, (w_n mu + w_s (tau + z)) / (w_n + w_s).
+* "scale_postfit" (Table II): a scale-ambiguous log-depth y minimising
+  c_semi + c_grad with tau held at 0 (the semi-dense depths' own scale), then
+  the least-squares fit of the scale to the network's log-depth,
+  tau = mean_i (mu_i - y_i) over all pixels, unweighted (reading R22), and
+  x = y + tau.
 """
 
 from __future__ import annotations
@@ -59,6 +70,7 @@ class SolverParams:
     cg_max: int = 4000
     huber_delta: float = 1.345
     linear_solver: str = "pcg"   # "pcg" or "direct"
+    variant: str = "full"        # "full" (Sec. II-C), "no_pairwise" (Table III), "scale_postfit" (Table II)
 
 
 # ---------------------------------------------------------------- Huber
@@ -255,7 +267,12 @@ class GNInfo:
 
 
 def gauss_newton(x0, tau0, prior: PriorMaps, semi: SemiMeasurements, params: SolverParams):
-    """The paper's alternating Gauss-Newton scheme (Sec. II-C; readings R13, R14)."""
+    """The paper's alternating Gauss-Newton scheme (Sec. II-C; readings R13, R14),
+    or one of its two ablations (Sec. III, Tables II and III)."""
+    if params.variant == "scale_postfit":
+        return scale_postfit(x0, tau0, prior, semi, params)
+    if params.variant not in ("full", "no_pairwise"):
+        raise ValueError(params.variant)
     delta = params.huber_delta
     H, W = prior.mu.shape
     x = np.array(x0, dtype=np.float64, copy=True)
@@ -263,17 +280,49 @@ def gauss_newton(x0, tau0, prior: PriorMaps, semi: SemiMeasurements, params: Sol
     info = GNInfo()
     for _ in range(params.n_gn):
         w_n, w_s, c_x, c_y = irls_weights(x, tau, prior, semi, delta)
-        A, b = normal_equations(w_n, w_s, c_x, c_y, tau, prior, semi)
-        if params.linear_solver == "direct":
-            xv = solve_direct(A, b)
-            its = -1
+        if params.variant == "no_pairwise":
+            # Table III: no gradient terms, so A is diagonal and the x-step is
+            # the per-pixel weighted mean of the two log-depth estimates
+            z = np.where(semi.valid, semi.z, 0.0)
+            x = (w_n * prior.mu + w_s * (tau + z)) / (w_n + w_s)
+            its = 0
         else:
-            xv, its = pcg(A, b, x.ravel(), params.n_cg, params.cg_rtol, params.cg_max)
-        x = xv.reshape(H, W)
+            A, b = normal_equations(w_n, w_s, c_x, c_y, tau, prior, semi)
+            if params.linear_solver == "direct":
+                xv = solve_direct(A, b)
+                its = -1
+            else:
+                xv, its = pcg(A, b, x.ravel(), params.n_cg, params.cg_rtol, params.cg_max)
+            x = xv.reshape(H, W)
         tau = scale_step(x, tau, semi, delta)
         info.cg_iterations.append(its)
         info.costs.append(cost(x, tau, prior, semi, delta))
     return x, tau, info
+
+
+def scale_postfit(x0, tau0, prior: PriorMaps, semi: SemiMeasurements, params: SolverParams):
+    """Table II's alternative to solving for the scale: n_gn IRLS Gauss-Newton
+    iterations on c_semi + c_grad alone with tau = 0, which gives a log-depth y
+    in the semi-dense depths' scale (warm start y = x0 - tau0), then the
+    least-squares fit of a global log-scale offset to the network log-depth,
+    tau = mean(mu - y) (reading R22). Returns (y + tau, tau, info)."""
+    delta = params.huber_delta
+    H, W = prior.mu.shape
+    y = np.array(x0, dtype=np.float64, copy=True) - float(tau0)
+    info = GNInfo()
+    zeros = np.zeros((H, W))
+    for _ in range(params.n_gn):
+        _, w_s, c_x, c_y = irls_weights(y, 0.0, prior, semi, delta)
+        A, b = normal_equations(zeros, w_s, c_x, c_y, 0.0, prior, semi)   # no network term
+        if params.linear_solver == "direct":
+            yv = solve_direct(A, b)
+            its = -1
+        else:
+            yv, its = pcg(A, b, y.ravel(), params.n_cg, params.cg_rtol, params.cg_max)
+        y = yv.reshape(H, W)
+        info.cg_iterations.append(its)
+    tau = float(np.mean(prior.mu - y))
+    return y + tau, tau, info
 
 
 def minimiser(prior: PriorMaps, semi: SemiMeasurements, delta, x0=None, tau0: float = 0.0,

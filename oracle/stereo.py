@@ -96,6 +96,8 @@ class SearchResult:
     var_d: np.ndarray      # sigma_d^2 of eq. (semi)
     rho_obs: np.ndarray    # 1 / d*
     var_obs: np.ndarray    # sigma_d^2 / d*^4
+    tap_margin: np.ndarray = None    # (npix, N_s) px from the sample's nearest tap to the image edge (< 0: outside)
+    range_margin: np.ndarray = None  # (npix, N_s) min(rho_k - rho_min, rho_max - rho_k) / rho_k (< 0: outside)
 
 
 def _pattern(I0f, u, v, l0x, l0y, pattern, dt):
@@ -214,6 +216,8 @@ def epipolar_search(I0, I1, K, T_wc0, T_wc1, rho, var, valid, mask,
 
     ssd = np.full((n, NS), np.inf, dtype=dt)
     rho_k = np.zeros((n, NS), dtype=dt)
+    tap_margin = np.full((n, NS), -np.inf)
+    range_margin = np.full((n, NS), -np.inf)
     half = dt.type((NS - 1) / 2.0)
     for k in range(NS):
         off = dt.type(k) - half
@@ -228,6 +232,14 @@ def epipolar_search(I0, I1, K, T_wc0, T_wc1, rho, var, valid, mask,
         taps = _taps(params.pattern, offs, pkx, pky, lx, ly)
         for (tu, tv) in taps:
             ok &= _inside(tu, tv, W, H)
+        # how far each validity test is from its boundary (reported, not used)
+        tm = np.full(n, np.inf)
+        for (tu, tv) in taps:
+            tm = np.minimum(tm, np.minimum(np.minimum(tu, W - 1 - tu), np.minimum(tv, H - 1 - tv)))
+        tap_margin[:, k] = np.where(live, tm, -np.inf)
+        with np.errstate(invalid="ignore", divide="ignore"):
+            rm = np.minimum(rk - rmin, rmax - rk) / rk
+        range_margin[:, k] = np.where(live & np.isfinite(rk), rm, -np.inf)
         s = np.zeros(n, dtype=dt)
         for j, (tu, tv) in enumerate(taps):
             cu = np.clip(np.where(ok, tu, dt.type(0)), 0, W - 1).astype(dt)
@@ -287,7 +299,7 @@ def epipolar_search(I0, I1, K, T_wc0, T_wc1, rho, var, valid, mask,
     nb_out = np.where(fin, nb, -1)
     return SearchResult(pix, status, ssd, rho_k, kb_out, nb_out,
                         np.where(fin, lam, 0), np.where(fin, d_star, 0), np.where(fin, var_d, 0),
-                        np.where(fin, rho_o, 0), np.where(fin, var_o, 0))
+                        np.where(fin, rho_o, 0), np.where(fin, var_o, 0), tap_margin, range_margin)
 
 
 def filter_update(rho, var, valid, pix, rho_obs, var_obs):

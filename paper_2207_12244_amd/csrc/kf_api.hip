@@ -46,6 +46,9 @@ const char* validate(const kf_config& c) {
   if (c.solver_cooperative != 0 && c.solver_cooperative != 1) return "solver_cooperative must be 0 or 1";
   if (c.pipeline_frames != 0 && c.pipeline_frames != 1) return "pipeline_frames must be 0 or 1";
   if (c.cg_variant < 0 || c.cg_variant > 2) return "cg_variant must be 0, 1 or 2";
+  if (c.variant < KF_VARIANT_FULL || c.variant > KF_VARIANT_SCALE_POSTFIT) return "unknown variant";
+  if (!(c.lambda_trans >= 0.0) || !std::isfinite(c.lambda_trans)) return "lambda_trans must be finite and >= 0";
+  if (c.lambda_inliers < 0) return "lambda_inliers must be >= 0";
   if (c.cg_variant == 2 && c.cg_rtol > 0.0) return "the pipelined CG variant runs a fixed iteration count (cg_rtol = 0)";
   if (!(c.solver_timeout_ms >= 0.0) || !std::isfinite(c.solver_timeout_ms) || c.solver_timeout_ms > 3.6e6)
     return "solver_timeout_ms must be in [0, 3.6e6]";
@@ -258,6 +261,7 @@ bool frame_constants(const kf_ctx* c, const double* T1, FrameConst* fc) {
     fc->b[i] = s;
     c1[i] = s2;
   }
+  fc->trans = std::sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
   for (int i = 0; i < 3; ++i) {
     double s = 0.0;
     for (int k = 0; k < 3; ++k) s += K[i * 3 + k] * c1[k];
@@ -296,6 +300,7 @@ bool stereo_args(kf_ctx* c, const uint8_t* image1, const double* T_wc1, StereoAr
   a->rho_out = a->rho;
   a->var_out = a->var;
   a->match = ws_ptr<int32_t>(c, c->lay.match);
+  a->buf = c->cur;
   return true;
 }
 
@@ -307,6 +312,11 @@ uint32_t solve_epoch_bound(const kf_config& g) {
 }
 
 bool solve_pipelined(const kf_config& g) { return g.cg_variant == 2 || (g.cg_variant == 0 && g.cg_rtol == 0.0); }
+
+int solve_kind(const kf_config& g) {
+  const bool var = g.variant != KF_VARIANT_FULL || g.lambda_trans > 0.0 || g.lambda_inliers > 0;
+  return (solve_pipelined(g) ? 1 : 0) | (var ? 2 : 0);
+}
 
 void solve_args(kf_ctx* c, SolveArgs* a) {
   const kf_config& g = c->cfg;
@@ -330,6 +340,10 @@ void solve_args(kf_ctx* c, SolveArgs* a) {
   a->n_gn = g.n_gn;
   a->n_cg = g.n_cg;
   a->cg_max = g.cg_max;
+  a->variant = g.variant;
+  a->lambda_inliers = g.lambda_inliers;
+  a->buf = c->cur;
+  a->lambda_trans = g.lambda_trans;
   a->cg_rtol = g.cg_rtol;
   a->huber_delta = g.huber_delta;
   a->r_floor = g.r_floor;
@@ -469,13 +483,15 @@ const char* kf_status_string(int32_t s) {
   return "unknown status";
 }
 
-kf_status kf_set_prior(kf_ctx* c, const uint8_t* image0, const void* logdepth, const void* logdepth_var,
-                       const void* grad_x, const void* grad_x_var, const void* grad_y, const void* grad_y_var,
-                       const double T_wc0[16]) {
-  if (!c) return KF_ERR_ARG;
-  if (!image0 || !logdepth || !logdepth_var || !grad_x || !grad_x_var || !grad_y || !grad_y_var)
-    return fail(c, KF_ERR_ARG, "kf_set_prior: NULL buffer");
-  if (!pose_ok(T_wc0)) return fail(c, KF_ERR_ARG, "kf_set_prior: pose must be finite with last row 0 0 0 1");
+}  // extern "C"
+
+namespace {
+
+// New keyframe: clears the state, then (with `rs`) resamples the network's maps
+// into the prior region and initialises from there in place, else initialises
+// from the six caller maps.
+kf_status set_prior_impl(kf_ctx* c, const uint8_t* image0, const void* const maps[6], const double* T_wc0,
+                         const ResampleArgs* rs) {
   std::memcpy(c->T_wc0, T_wc0, sizeof(c->T_wc0));
   // exchange words and device scalars start from zero (epoch 0 is never used)
   hipError_t e = wait_solves(c);
@@ -489,7 +505,20 @@ kf_status kf_set_prior(kf_ctx* c, const uint8_t* image0, const void* logdepth, c
   a.W = c->cfg.width;
   a.H = c->cfg.height;
   a.image0 = image0;
-  a.mu = logdepth; a.var_n = logdepth_var; a.gx = grad_x; a.var_gx = grad_x_var; a.gy = grad_y; a.var_gy = grad_y_var;
+  const void* src[6];
+  const size_t N = (size_t)a.W * a.H;
+  if (rs) {
+    ResampleArgs r = *rs;
+    r.W = a.W;
+    r.H = a.H;
+    r.dst = c->ws + c->lay.prior;
+    e = launch_resample_priors(c->cfg.precision, r, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "kf_set_prior_network (resample)");
+    for (int k = 0; k < 6; ++k) src[k] = c->ws + c->lay.prior + k * N * c->lay.elt;
+  } else {
+    for (int k = 0; k < 6; ++k) src[k] = maps[k];
+  }
+  a.mu = src[0]; a.var_n = src[1]; a.gx = src[2]; a.var_gx = src[3]; a.gy = src[4]; a.var_gy = src[5];
   a.i0 = c->ws + c->lay.i0;
   a.prior = c->ws + c->lay.prior;
   a.x = c->ws + c->lay.x;
@@ -508,6 +537,41 @@ kf_status kf_set_prior(kf_ctx* c, const uint8_t* image0, const void* logdepth, c
   return KF_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+kf_status kf_set_prior(kf_ctx* c, const uint8_t* image0, const void* logdepth, const void* logdepth_var,
+                       const void* grad_x, const void* grad_x_var, const void* grad_y, const void* grad_y_var,
+                       const double T_wc0[16]) {
+  if (!c) return KF_ERR_ARG;
+  if (!image0 || !logdepth || !logdepth_var || !grad_x || !grad_x_var || !grad_y || !grad_y_var)
+    return fail(c, KF_ERR_ARG, "kf_set_prior: NULL buffer");
+  if (!pose_ok(T_wc0)) return fail(c, KF_ERR_ARG, "kf_set_prior: pose must be finite with last row 0 0 0 1");
+  const void* maps[6] = {logdepth, logdepth_var, grad_x, grad_x_var, grad_y, grad_y_var};
+  return set_prior_impl(c, image0, maps, T_wc0, nullptr);
+}
+
+kf_status kf_set_prior_network(kf_ctx* c, const uint8_t* image0, const void* logdepth, const void* logdepth_var,
+                               const void* grad_x, const void* grad_x_var, const void* grad_y, const void* grad_y_var,
+                               int32_t net_width, int32_t net_height, double focal_ref, const double T_wc0[16]) {
+  if (!c) return KF_ERR_ARG;
+  if (!image0 || !logdepth || !logdepth_var || !grad_x || !grad_x_var || !grad_y || !grad_y_var)
+    return fail(c, KF_ERR_ARG, "kf_set_prior_network: NULL buffer");
+  if (net_width < 2 || net_height < 2 || net_width > 8192 || net_height > 8192)
+    return fail(c, KF_ERR_ARG, "kf_set_prior_network: network size must be in [2, 8192]");
+  if (!(focal_ref > 0.0) || !std::isfinite(focal_ref))
+    return fail(c, KF_ERR_ARG, "kf_set_prior_network: focal_ref must be finite and > 0");
+  if (!pose_ok(T_wc0)) return fail(c, KF_ERR_ARG, "kf_set_prior_network: pose must be finite with last row 0 0 0 1");
+  ResampleArgs r{};
+  r.Wn = net_width;
+  r.Hn = net_height;
+  const void* maps[6] = {logdepth, logdepth_var, grad_x, grad_x_var, grad_y, grad_y_var};
+  for (int k = 0; k < 6; ++k) r.src[k] = maps[k];
+  r.shift = std::log(c->cfg.fx * ((double)net_width / c->cfg.width) / focal_ref);
+  return set_prior_impl(c, image0, maps, T_wc0, &r);
+}
+
 kf_status kf_stereo_update(kf_ctx* c, const uint8_t* image1, const double T_wc1[16]) {
   if (!c) return KF_ERR_ARG;
   if (!c->has_prior) return fail(c, KF_ERR_STATE, "kf_stereo_update before kf_set_prior");
@@ -522,9 +586,9 @@ kf_status kf_stereo_update(kf_ctx* c, const uint8_t* image1, const double T_wc1[
     // solve before last may still be reading
     a.rho_out = rho_buf(c, nxt);
     a.var_out = var_buf(c, nxt);
+    a.buf = nxt;
     if (c->solve_pending[nxt]) e = hipStreamWaitEvent(c->stream, c->ev_solve[nxt], 0);
   }
-  if (e == hipSuccess) e = launch_zero(&scal_ptr(c)->n_updated, sizeof(int32_t), c->stream);
   if (e == hipSuccess)
     e = launch_stereo(c->cfg.precision, c->cfg.pattern, c->cfg.n_samples, a, c->stereo_blocks, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "kf_stereo_update");
@@ -545,8 +609,8 @@ kf_status kf_solve(kf_ctx* c) {
   if (e != hipSuccess) return hip_fail(c, e, "kf_solve (epoch wrap)");
   SolveArgs a;
   solve_args(c, &a);
-  const bool pipelined = solve_pipelined(g);
-  if (c->coresident < 0) c->coresident = solve_max_coresident(g.precision, c->tiling, pipelined, c->device);
+  const int kind = solve_kind(g);
+  if (c->coresident < 0) c->coresident = solve_max_coresident(g.precision, c->tiling, kind, c->device);
   if (c->coresident < c->tiling.blocks)
     return fail(c, KF_ERR_ARG, "solver tiling needs " + std::to_string(c->tiling.blocks) +
                                " co-resident workgroups, the device holds " + std::to_string(c->coresident));
@@ -559,7 +623,7 @@ kf_status kf_solve(kf_ctx* c) {
     if (e == hipSuccess) e = hipStreamWaitEvent(s, c->ev_user, 0);
     if (e != hipSuccess) return hip_fail(c, e, "kf_solve (ordering)");
   }
-  e = launch_solve(g.precision, c->tiling, a, g.solver_cooperative != 0, pipelined, s);
+  e = launch_solve(g.precision, c->tiling, a, g.solver_cooperative != 0, kind, s);
   if (e == hipSuccess && g.pipeline_frames) {
     e = hipEventRecord(c->ev_solve[c->cur], s);
     c->solve_pending[c->cur] = true;
@@ -611,13 +675,36 @@ kf_status kf_read_stats(kf_ctx* c, kf_frame_stats* out) {
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "kf_read_stats");
   out->n_searched = h.mask_count;
-  out->n_updated = h.n_updated;
+  out->n_updated = h.n_updated[c->cur];
   out->n_valid = h.n_valid;
   out->cg_iterations = h.cg_iterations;
   out->scale = std::exp(h.tau);
   out->cg_rel_residual = h.cg_rel_residual;
+  out->team_syncs = h.team_syncs;
+  out->new_keyframe = h.new_keyframe;
   if (h.err & ERR_TIMEOUT) return fail(c, KF_ERR_TIMEOUT, "solver workgroups timed out waiting for their team");
   if (h.err & ERR_INPUT) return fail(c, KF_ERR_INPUT, "device found a non-finite input or a variance <= 0");
+  return KF_OK;
+}
+
+kf_status kf_probe_sync(kf_ctx* c, int32_t rounds, int32_t nvalues) {
+  if (!c) return KF_ERR_ARG;
+  if (!c->has_prior) return fail(c, KF_ERR_STATE, "kf_probe_sync before kf_set_prior");
+  if (c->cfg.pipeline_frames) return fail(c, KF_ERR_STATE, "kf_probe_sync needs a context without pipeline_frames");
+  if (rounds < 1 || rounds > 20000) return fail(c, KF_ERR_ARG, "kf_probe_sync: rounds must be in [1, 20000]");
+  if (nvalues < 1 || nvalues > NV_MAX) return fail(c, KF_ERR_ARG, "kf_probe_sync: nvalues must be in [1, 3]");
+  const uint32_t bound = (uint32_t)rounds + 2;
+  hipError_t e = epoch_wrap_if_needed(c, bound);
+  if (e != hipSuccess) return hip_fail(c, e, "kf_probe_sync (epoch wrap)");
+  SolveArgs a;
+  solve_args(c, &a);
+  a.epoch_span = bound;
+  a.packed = (c->cfg.precision != KF_F64 && bound < 30000) ? 1 : 0;
+  if (c->coresident < 0) c->coresident = solve_max_coresident(c->cfg.precision, c->tiling, solve_kind(c->cfg), c->device);
+  if (c->coresident < c->tiling.blocks) return fail(c, KF_ERR_ARG, "kf_probe_sync: tiling not co-resident");
+  e = launch_sync_probe(c->cfg.precision, c->tiling, a, rounds, nvalues, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "kf_probe_sync");
+  c->epoch += bound;
   return KF_OK;
 }
 

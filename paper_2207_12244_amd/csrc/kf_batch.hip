@@ -46,6 +46,7 @@ struct kf_batch {
   int device = 0;
   int prec = 0, pattern = 0, ns = 0, threads = 0, ppt = 0;
   bool pipelined = false;
+  int kind = 0;                 // solve_kind of the launch: pipelined bit | any member's variant bit
   size_t smem = 0;
   int grid = 0;                    // solver workgroups
   int max_queue = 0;               // longest per-workgroup queue of the last schedule
@@ -153,7 +154,7 @@ hipError_t enqueue(kf_batch* b, int which, hipStream_t s) {
   if (which != 2)
     e = launch_stereo_batch(b->prec, b->pattern, b->ns, b->d_st(), b->d_n(), (int)b->m.size(), b->stereo_blocks, s);
   if (e == hipSuccess && which != 1)
-    e = launch_solve_batch(b->prec, b->threads, b->ppt, b->pipelined, b->d_so, b->d_queue(), b->d_qoff(), b->grid,
+    e = launch_solve_batch(b->prec, b->threads, b->ppt, b->kind, b->d_so, b->d_queue(), b->d_qoff(), b->grid,
                            b->smem, s);
   return e;
 }
@@ -295,6 +296,8 @@ kf_status kf_batch_create(kf_ctx* const* members, int32_t n, const kf_batch_conf
   b->ns = c0->cfg.n_samples;
   b->threads = c0->tiling.threads;
   b->pipelined = solve_pipelined(c0->cfg);
+  b->kind = b->pipelined ? 1 : 0;
+  for (int i = 0; i < n; ++i) b->kind |= solve_kind(members[i]->cfg) & 2;
   b->use_graph = cfg->use_graph != 0;
   b->stereo_blocks = c0->stereo_blocks;
   b->dl = dl;
@@ -315,7 +318,7 @@ kf_status kf_batch_create(kf_ctx* const* members, int32_t n, const kf_batch_conf
   }
   // LDS: the largest member's need (team partials + the three rings of its tile)
   b->smem = smem;
-  b->capacity = solve_batch_coresident(b->prec, b->threads, b->ppt, b->pipelined, b->smem, b->device);
+  b->capacity = solve_batch_coresident(b->prec, b->threads, b->ppt, b->kind, b->smem, b->device);
   if (b->capacity < maxB) {
     delete b;
     return KF_ERR_ARG;

@@ -84,14 +84,17 @@ template <> struct Form<KF_BF16_F32> { using T = float; using TI = bf16; };
 struct DevScalars {
   double tau;             // ln s
   double cg_rel_residual;
+  double frame_trans[2];  // camera-centre distance of the frame behind filter-state buffer b from the keyframe
   int32_t mask_count;     // textured pixels (length of the search list)
-  int32_t n_updated;      // measurements produced by the last stereo update
+  int32_t n_updated[2];   // measurements of the stereo update that wrote filter-state buffer b
   int32_t n_valid;        // pixels with a filter estimate (computed by the solver)
   int32_t cg_iterations;
   int32_t err;            // bit flags, ERR_*
   uint32_t epoch;         // next synchronisation epoch of the solver team (never 0)
-  int32_t pad[6];
+  int32_t team_syncs;     // team synchronisations of the last solve
+  int32_t new_keyframe;   // KF_NEW_KEYFRAME_* bits of the last solve (0: fused)
 };
+static_assert(sizeof(DevScalars) <= 256, "device scalars take one 256-byte block of the workspace");
 enum : int32_t { ERR_INPUT = 1, ERR_TIMEOUT = 2 };
 
 // ------------------------------------------------------------------ workspace layout
@@ -116,7 +119,9 @@ constexpr int CHUNK = 256;           // pixels per compaction chunk
 bool choose_tiling(int W, int H, int tx_req, int ty_req, int threads_req, int prec, Tiling* t);
 double iteration_us(const Tiling& t);   // latency model of one PCG iteration
 // Workgroups of this tiling the device can hold at once (0 if unknown).
-int solve_max_coresident(int prec, const Tiling& t, bool pipelined, int device);
+// kind: bit 0 pipelined CG, bit 1 the solver instantiation that handles the
+// Sec. III variants and the keyframe rule (solve_kind)
+int solve_max_coresident(int prec, const Tiling& t, int kind, int device);
 bool layout_for(const kf_config& cfg, const Tiling& t, Layout* lay);
 int stage_stride(int W);
 
@@ -136,12 +141,20 @@ struct PriorArgs {
   int border;
 };
 
+struct ResampleArgs {        // network outputs at the network's size -> keyframe priors
+  int W, H, Wn, Hn;
+  const void* src[6];        // mu, var_mu, g_x, var_gx, g_y, var_gy (Wn x Hn, map element type)
+  void* dst;                 // T[6][W H], same order
+  double shift;              // ln(focal length at the network's size / reference focal length)
+};
+
 struct FrameConst {          // epipolar constants of one frame (host FP64)
   double Hm[9];              // K R K^-1
   double b[3];               // K t
   double e0[3];              // keyframe epipole K c1 (homogeneous)
   double rho_min, rho_max;
   double sigma_photo;
+  double trans;              // |t|: distance between the two camera centres
 };
 
 struct StereoArgs {
@@ -156,6 +169,7 @@ struct StereoArgs {
   void* rho; void* var;       // filter state read
   void* rho_out; void* var_out;   // filter state written (== rho / var: in place)
   int32_t* match;
+  int buf;                   // filter-state buffer written (its counters: n_updated[buf], frame_trans[buf])
   FrameConst fc;
 };
 
@@ -172,6 +186,10 @@ struct SolveArgs {
   uint32_t epoch_span;       // epochs one launch may use (the base lives in DevScalars::epoch)
   int packed;                // 1: one-word partials (48-bit values, 16-bit epochs)
   int n_gn, n_cg, cg_max;
+  int variant;               // kf_variant
+  int lambda_inliers;        // keyframe rule (0: off)
+  int buf;                   // filter-state buffer read (the counters its stereo update wrote)
+  double lambda_trans;       // keyframe rule (0: off)
   double cg_rtol;
   double huber_delta, r_floor;
   uint64_t timeout_ticks;    // wall-clock ticks a workgroup may wait for its team
@@ -193,19 +211,21 @@ struct ImportArgs {
 // ------------------------------------------------------------------ launchers (return hipError_t)
 
 hipError_t launch_prior(int prec, const PriorArgs& a, hipStream_t s);
+hipError_t launch_resample_priors(int prec, const ResampleArgs& a, hipStream_t s);
 hipError_t launch_stereo(int prec, int pattern, int ns, const StereoArgs& a, int blocks, hipStream_t s);
 // Batched stereo: the active count *n (device, <= nmax) and the table entries
 // are read by the kernels, so the launches can be captured once.
 hipError_t launch_stereo_batch(int prec, int pattern, int ns, const StereoArgs* tab, const int32_t* n, int nmax,
                                int blocks, hipStream_t s);
-hipError_t launch_solve(int prec, const Tiling& t, const SolveArgs& a, bool cooperative, bool pipelined,
-                        hipStream_t s);
+hipError_t launch_solve(int prec, const Tiling& t, const SolveArgs& a, bool cooperative, int kind, hipStream_t s);
 // Batched solver: workgroup g runs the team members queue[qoff[g] .. qoff[g+1])
 // in order, each entry (keyframe << 8) | member; all `grid` workgroups must be
 // co-resident.
-hipError_t launch_solve_batch(int prec, int threads, int ppt, bool pipelined, const SolveArgs* tab,
+hipError_t launch_solve_batch(int prec, int threads, int ppt, int kind, const SolveArgs* tab,
                               const int32_t* queue, const int32_t* qoff, int grid, size_t smem, hipStream_t s);
-int solve_batch_coresident(int prec, int threads, int ppt, bool pipelined, size_t smem, int device);
+// Team-synchronisation probe on the layout of `a` (see k_sync_probe).
+hipError_t launch_sync_probe(int prec, const Tiling& t, const SolveArgs& a, int rounds, int nv, hipStream_t s);
+int solve_batch_coresident(int prec, int threads, int ppt, int kind, size_t smem, int device);
 bool solve_batch_supported(int prec, int threads, int ppt);
 hipError_t launch_read(int prec, const ReadArgs& a, hipStream_t s);
 hipError_t launch_import(int prec, const ImportArgs& a, hipStream_t s);
@@ -251,6 +271,7 @@ bool pose_ok(const double* T);
 bool stereo_args(kf_ctx* c, const uint8_t* image1, const double* T_wc1, StereoArgs* a);
 uint32_t solve_epoch_bound(const kf_config& g);
 bool solve_pipelined(const kf_config& g);
+int solve_kind(const kf_config& g);
 void solve_args(kf_ctx* c, SolveArgs* a);
 hipError_t epoch_wrap_if_needed(kf_ctx* c, uint32_t bound);   // restart epochs before they could wrap
 

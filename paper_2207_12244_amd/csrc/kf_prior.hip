@@ -59,9 +59,39 @@ __global__ __launch_bounds__(CHUNK) void k_prior_init(PriorArgs a) {
     a.scal->epoch = 1u;
     a.scal->tau = 0.0;
     a.scal->cg_rel_residual = 0.0;
-    a.scal->n_updated = 0;
+    a.scal->n_updated[0] = a.scal->n_updated[1] = 0;
     a.scal->n_valid = 0;
     a.scal->cg_iterations = 0;
+  }
+}
+
+// Network outputs (Sec. II-A) to keyframe priors: bilinear resampling with pixel
+// centres aligned (keyframe pixel u samples the network map at
+// (u + 1/2) Wn / W - 1/2, clamped), the focal-length shift of the log-depth, and
+// the gradients and their variances rescaled from network to keyframe pixel
+// spacing. Positions, weights and sums in FP64.
+template <typename T>
+__global__ __launch_bounds__(256) void k_resample_priors(ResampleArgs r) {
+  const int N = r.W * r.H;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= N) return;
+  const int u = i % r.W, v = i / r.W;
+  const double sx = (double)r.Wn / r.W, sy = (double)r.Hn / r.H;
+  double un = (u + 0.5) * sx - 0.5, vn = (v + 0.5) * sy - 0.5;
+  un = un < 0.0 ? 0.0 : (un > r.Wn - 1.0 ? r.Wn - 1.0 : un);
+  vn = vn < 0.0 ? 0.0 : (vn > r.Hn - 1.0 ? r.Hn - 1.0 : vn);
+  const int u0 = min((int)floor(un), r.Wn - 2), v0 = min((int)floor(vn), r.Hn - 2);
+  const double f = un - u0, g = vn - v0;
+  const double scale[6] = {1.0, 1.0, sx, sx * sx, sy, sy * sy};
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const T* m = static_cast<const T*>(r.src[k]);
+    const size_t a = (size_t)v0 * r.Wn + u0, b = a + r.Wn;
+    const double top = (1.0 - f) * (double)m[a] + f * (double)m[a + 1];
+    const double bot = (1.0 - f) * (double)m[b] + f * (double)m[b + 1];
+    double val = (1.0 - g) * top + g * bot;
+    val = k == 0 ? val + r.shift : val * scale[k];
+    static_cast<T*>(r.dst)[(size_t)k * N + i] = (T)val;
   }
 }
 
@@ -162,6 +192,15 @@ hipError_t launch_prior(int prec, const PriorArgs& a, hipStream_t s) {
     case KF_BF16_F32: return prior_impl<KF_BF16_F32>(a, s);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_resample_priors(int prec, const ResampleArgs& a, hipStream_t s) {
+  const int blocks = (a.W * a.H + 255) / 256;
+  if (prec == KF_F64)
+    hipLaunchKernelGGL(k_resample_priors<double>, dim3(blocks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_resample_priors<float>, dim3(blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_read(int prec, const ReadArgs& a, hipStream_t s) {

@@ -326,17 +326,26 @@ struct Team {
   }
 };
 
-// One member (tile b) of the team that solves keyframe `a`; every thread of
-// the workgroup calls it. LDS: `smem` as sized by smem_for for this team.
-template <typename T, int NT, int PPT, bool PIPE>
-__device__ __forceinline__ void solve_member(const SolveArgs& a, const int b, unsigned char* smem) {
-  constexpr int NW = NT / 64;
-  const int B = a.tiles_x * a.tiles_y;
-  const int tid = threadIdx.x;
-  const int W = a.W, H = a.H, N = W * H;
+// LDS of one member: [NW][NV_MAX] wave partials, [NV_MAX][CPV] team chunk
+// partials, abort flag, then three rings of (tile_h + 2) x (tile_w + 2):
+// x and two stencil operands.
+template <typename T, int NT>
+struct MemberLds {
+  T* xs;
+  T* ps;
+  T* ms0;
+};
 
-  Team<T, NT> tm;
-  tm.B = B;
+// Sets up member b (tile b) of the team of `a`: tile geometry, neighbours,
+// exchange words, LDS carve-up (cleared) and this thread's ghost slots (top
+// row, bottom row, left column, right column). Ends with a workgroup barrier.
+template <typename T, int NT>
+__device__ __forceinline__ void team_init(Team<T, NT>& tm, MemberLds<T, NT>& lds, const SolveArgs& a, const int b,
+                                          unsigned char* smem) {
+  constexpr int NW = NT / 64;
+  const int tid = threadIdx.x;
+  const int W = a.W, H = a.H;
+  tm.B = a.tiles_x * a.tiles_y;
   tm.b = b;
   const int bx = b % a.tiles_x, by = b / a.tiles_x;
   const int ox = bx * a.tile_w, oy = by * a.tile_h;
@@ -350,32 +359,23 @@ __device__ __forceinline__ void solve_member(const SolveArgs& a, const int b, un
   tm.nb_dn = by < a.tiles_y - 1 ? b + a.tiles_x : -1;
   tm.nb_lf = bx > 0 ? b - 1 : -1;
   tm.nb_rt = bx < a.tiles_x - 1 ? b + 1 : -1;
-  KF_GLOBAL DevScalars* scal = gp(a.scal);
   tm.parts = gp(a.parts);
   tm.halo = gp(a.halo);
-  tm.err = &scal->err;
+  tm.err = &gp(a.scal)->err;
   tm.limit = a.timeout_ticks;
   tm.packed = a.packed != 0;
-  // LDS: [NW][NV_MAX] wave partials, [NV_MAX][CPV] team chunk partials, abort flag,
-  // then three rings of (tile_h + 2) x (tile_w + 2): x, and two stencil operands
   double* dsm = reinterpret_cast<double*>(smem);
   tm.s_wred = dsm;
   tm.s_pol = tm.s_wred + NW * NV_MAX;
   tm.s_abort = reinterpret_cast<int*>(tm.s_pol + NV_MAX * Team<T, NT>::CPV);
   const int ring_max = (a.tile_h + 2) * (a.tile_w + 2);
-  T* xs = reinterpret_cast<T*>(dsm + NW * NV_MAX + NV_MAX * Team<T, NT>::CPV + 2);
-  T* ps = xs + ring_max;
-  T* ms0 = ps + ring_max;
-
-  const int tw = tm.tw, th = tm.th, rw = tm.rw;
-  const int npx = tw * th;
-  const T delta = (T)a.huber_delta;
-
-  for (int i = tid; i < 3 * ring_max; i += NT) xs[i] = (T)0;
+  lds.xs = reinterpret_cast<T*>(dsm + NW * NV_MAX + NV_MAX * Team<T, NT>::CPV + 2);
+  lds.ps = lds.xs + ring_max;
+  lds.ms0 = lds.ps + ring_max;
+  for (int i = tid; i < 3 * ring_max; i += NT) lds.xs[i] = (T)0;
   if (tid < NV_MAX * Team<T, NT>::CPV) tm.s_pol[tid] = 0.0;
   if (tid == 0) *tm.s_abort = 0;
-
-  // ghost slots: top row, bottom row, left column, right column
+  const int tw = tm.tw, th = tm.th, rw = tm.rw;
   const int nghost = 2 * tw + 2 * th;
 #pragma unroll
   for (int m = 0; m < GMAX; ++m) {
@@ -399,6 +399,30 @@ __device__ __forceinline__ void solve_member(const SolveArgs& a, const int b, un
     }
   }
   __syncthreads();
+}
+
+// One member (tile b) of the team that solves keyframe `a`; every thread of
+// the workgroup calls it. LDS: `smem` as sized by smem_for for this team.
+// VAR: instantiation that handles the Sec. III variants and the keyframe rule;
+// the plain form (variant FULL, no rule) runs the one without those branches
+// (they cost it ~1 % per solve).
+template <typename T, int NT, int PPT, bool PIPE, bool VAR>
+__device__ __forceinline__ void solve_member(const SolveArgs& a, const int b, unsigned char* smem) {
+  const int tid = threadIdx.x;
+  const int W = a.W, H = a.H, N = W * H;
+
+  Team<T, NT> tm;
+  MemberLds<T, NT> lds;
+  team_init(tm, lds, a, b, smem);
+  const int ox = (b % a.tiles_x) * a.tile_w, oy = (b / a.tiles_x) * a.tile_h;
+  KF_GLOBAL DevScalars* scal = gp(a.scal);
+  T* xs = lds.xs;
+  T* ps = lds.ps;
+  T* ms0 = lds.ms0;
+
+  const int tw = tm.tw, th = tm.th, rw = tm.rw;
+  const int npx = tw * th;
+  const T delta = (T)a.huber_delta;
 
   const KF_GLOBAL T* pr = gp(static_cast<const T*>(a.prior));
   const KF_GLOBAL T* mu_g = pr;
@@ -419,13 +443,25 @@ __device__ __forceinline__ void solve_member(const SolveArgs& a, const int b, un
 #define KF_LY(j) (lxy[j] >> 16)
 #define KF_LI(j) ((KF_LY(j) + 1) * rw + KF_LX(j) + 1)
 #define KF_GI(j) ((oy + KF_LY(j)) * W + ox + KF_LX(j))
+  // Table III drops the gradient terms; Table II solves a scale-ambiguous
+  // log-depth y = x - tau from the semi-dense and gradient terms (tau held at
+  // 0 inside the GN loop) and fits the scale afterwards
+  const bool nopair = VAR && a.variant == KF_VARIANT_NO_PAIRWISE;
+  const bool postfit = VAR && a.variant == KF_VARIANT_SCALE_POSTFIT;
+  double tau = scal->tau;
+  const T x_shift = postfit ? (T)tau : (T)0;
+  // keyframe rule (Sec. II): a frame that moved the camera too far from the
+  // keyframe, or whose semi-dense update found too few inliers, is not fused
+  int new_kf = 0;
+  if (VAR && a.lambda_trans > 0.0 && scal->frame_trans[a.buf] > a.lambda_trans) new_kf |= KF_NEW_KEYFRAME_TRANSLATION;
+  if (VAR && a.lambda_inliers > 0 && scal->n_updated[a.buf] < a.lambda_inliers) new_kf |= KF_NEW_KEYFRAME_INLIERS;
 #pragma unroll
   for (int j = 0; j < PPT; ++j) {
     const int k = tid + j * NT;
     lxy[j] = k < npx ? (((k / tw) << 16) | (k % tw)) : -1;
     xr[j] = rr[j] = pv[j] = dg[j] = idg[j] = cR[j] = cL[j] = cD[j] = cU[j] = (T)0;
     if (lxy[j] >= 0) {
-      xr[j] = x_g[KF_GI(j)];
+      xr[j] = x_g[KF_GI(j)] - x_shift;
       xs[KF_LI(j)] = xr[j];
     }
   }
@@ -435,10 +471,10 @@ __device__ __forceinline__ void solve_member(const SolveArgs& a, const int b, un
     if (tm.g_src[m] >= 0) {
       const int li_g = tm.g_li[m];
       const int gy_ = li_g / rw - 1, gx_ = li_g % rw - 1;
-      xs[li_g] = x_g[(oy + gy_) * W + ox + gx_];
+      xs[li_g] = x_g[(oy + gy_) * W + ox + gx_] - x_shift;
     }
   }
-  double tau = scal->tau;
+  if (postfit && !new_kf) tau = 0.0;
   __syncthreads();
 
   // epoch base of this launch: written by the previous launch's workgroup 0
@@ -468,7 +504,7 @@ __device__ __forceinline__ void solve_member(const SolveArgs& a, const int b, un
     return (T)1 / sqrt(R);
   };
 
-  for (int gn = 0; gn < a.n_gn; ++gn) {
+  for (int gn = 0; gn < (new_kf ? 0 : a.n_gn); ++gn) {
 #pragma unroll
     for (int j = 0; j < PPT; ++j) refresh(lxy[j]);
     // ---- IRLS weights and 5-point normal equations at (x, tau) (Sec. II-C);
@@ -481,13 +517,18 @@ __device__ __forceinline__ void solve_member(const SolveArgs& a, const int b, un
       const int i = KF_GI(j), l = KF_LI(j);
       const T xi = xr[j];
       const T mu = mu_g[i], isn = isn_g[i];
-      const T wn = huber_w((xi - mu) * isn, delta) * isn * isn;
+      const T wn = postfit ? (T)0 : huber_w((xi - mu) * isn, delta) * isn * isn;
       T zs;
       const T isr = semi(i, zs);
       T ws = (T)0;
       if (isr > (T)0) ws = huber_w((xi - (T)tau - zs) * isr, delta) * isr * isr;
       T bb = wn * mu + ws * ((T)tau + zs);
       T cr = 0, cl = 0, cd = 0, cu = 0;
+      if (nopair) {
+        // per-pixel weighted mean of the network and semi-dense log-depths
+        xr[j] = bb / (wn + ws);
+        continue;
+      }
       if (u < W - 1) {
         const T g = gx_g[i];
         cr = edge_weight(xi, xs[l + 1], g, isgx_g[i], delta);
@@ -510,7 +551,7 @@ __device__ __forceinline__ void solve_member(const SolveArgs& a, const int b, un
       }
       const T d = wn + ws + cr + cl + cd + cu;
       dg[j] = d;
-      idg[j] = (T)1 / d;
+      idg[j] = d > (T)0 ? (T)1 / d : (T)0;   // d = 0 only without network and gradient terms
       cR[j] = cr; cL[j] = cl; cD[j] = cd; cU[j] = cu;
       const T ax = d * xi - cr * xs[l + 1] - cl * xs[l - 1] - cd * xs[l + rw] - cu * xs[l - rw];
       const T r = bb - ax;
@@ -522,6 +563,9 @@ __device__ __forceinline__ void solve_member(const SolveArgs& a, const int b, un
       r2 += (double)r * (double)r;
       b2 += (double)bb * (double)bb;
     }
+    int it = 0;
+    T qv[PPT];
+    if (!nopair) {
     vals[0] = rz; vals[1] = r2; vals[2] = b2;
     if (!tm.sync(e++, tol_mode ? 3 : 1, vals, tot, gval, true, ps, true)) return;
     double rz_t = tot[0];
@@ -532,8 +576,6 @@ __device__ __forceinline__ void solve_member(const SolveArgs& a, const int b, un
       converged = sqrt(tot[1]) <= a.cg_rtol * bnorm;
     }
 
-    int it = 0;
-    T qv[PPT];
     if (PIPE) {
       // Pipelined Jacobi PCG (Ghysels and Vanroose): the same iterates as the
       // textbook recurrences in exact arithmetic, with the two inner products
@@ -683,6 +725,7 @@ __device__ __forceinline__ void solve_member(const SolveArgs& a, const int b, un
         if (tm.g_src[m] >= 0) ps[tm.g_li[m]] = fma(be, ps[tm.g_li[m]], gval[m]);
       __syncthreads();
     }
+    }   // !nopair
     cg_total += it;
 
     // ---- scale step: semi weights at (x_new, tau), tau = sum w (x - z) / sum w (R13)
@@ -705,13 +748,27 @@ __device__ __forceinline__ void solve_member(const SolveArgs& a, const int b, un
     vals[0] = num; vals[1] = den; vals[2] = cnt;
     // the neighbours' x lands directly in the ghost ring of xs
     if (!tm.sync(e++, 3, vals, tot, gval, true, xs, true)) return;
-    if (tot[1] > 0.0) tau = tot[0] / tot[1];
+    if (!postfit && tot[1] > 0.0) tau = tot[0] / tot[1];
     n_valid = tot[2];
+  }
+  if (postfit && !new_kf) {
+    // least-squares fit of the log-scale to the network: tau = mean(mu - y)
+    double dev = 0.0;
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      refresh(lxy[j]);
+      if (lxy[j] >= 0) dev += (double)mu_g[KF_GI(j)] - (double)xr[j];
+    }
+    vals[0] = dev;
+    if (!tm.sync(e++, 1, vals, tot, gval, false)) return;
+    tau = tot[0] / (double)N;
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) xr[j] += (T)tau;
   }
 
 #pragma unroll
   for (int j = 0; j < PPT; ++j)
-    if (lxy[j] >= 0) x_g[KF_GI(j)] = xr[j];
+    if (lxy[j] >= 0 && !new_kf) x_g[KF_GI(j)] = xr[j];
 #undef KF_LX
 #undef KF_LY
 #undef KF_LI
@@ -723,14 +780,16 @@ __device__ __forceinline__ void solve_member(const SolveArgs& a, const int b, un
     scal->tau = tau;
     scal->cg_iterations = cg_total;
     scal->cg_rel_residual = relres;
-    scal->n_valid = (int32_t)n_valid;
+    if (!new_kf) scal->n_valid = (int32_t)n_valid;
+    scal->team_syncs = (int32_t)(e - e0);
+    scal->new_keyframe = new_kf;
   }
 }
 
-template <typename T, int NT, int PPT, bool PIPE>
+template <typename T, int NT, int PPT, bool PIPE, bool VAR>
 __global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  solve_member<T, NT, PPT, PIPE>(a, blockIdx.x, smem);
+  solve_member<T, NT, PPT, PIPE, VAR>(a, blockIdx.x, smem);
 }
 
 // Batched form: workgroup g works through its queue of (keyframe, member)
@@ -740,7 +799,7 @@ __global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
 // workgroups of up to 4 pixels per thread are held to 128 registers so that two
 // of them share a compute unit (one computes while the other's team
 // synchronises).
-template <typename T, int NT, int PPT, bool PIPE>
+template <typename T, int NT, int PPT, bool PIPE, bool VAR>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && NT == 512 && NT * PPT <= 2048 ? 4 : 1)))
 void k_solve_batch(const SolveArgs* __restrict__ tab,
                                                     const int32_t* __restrict__ queue,
@@ -751,7 +810,36 @@ void k_solve_batch(const SolveArgs* __restrict__ tab,
     const int32_t ent = queue[q];
     const SolveArgs a = tab[ent >> 8];
     __syncthreads();   // the previous member's last LDS reads are done
-    solve_member<T, NT, PPT, PIPE>(a, ent & 255, smem);
+    solve_member<T, NT, PPT, PIPE, VAR>(a, ent & 255, smem);
+  }
+}
+
+// Synchronisation probe: the team of `a` makes `rounds` exchanges of the kind
+// a pipelined PCG iteration makes (nv partial sums and the tile boundary of a
+// stencil operand, through the same Team::sync) with no arithmetic between
+// them, so launch time / rounds is the cost of one team synchronisation at
+// this layout.
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_sync_probe(SolveArgs a, int rounds, int nv) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  Team<T, NT> tm;
+  MemberLds<T, NT> lds;
+  team_init(tm, lds, a, blockIdx.x, smem);
+  KF_GLOBAL DevScalars* scal = gp(a.scal);
+  const uint32_t e0 = scal->epoch;
+  uint32_t e = e0;
+  double vals[NV_MAX], tot[NV_MAX];
+  T gval[GMAX];
+#pragma unroll
+  for (int v = 0; v < NV_MAX; ++v) vals[v] = (double)threadIdx.x;
+  for (int r = 0; r < rounds; ++r) {
+    T* ring = (r & 1) ? lds.ps : lds.ms0;
+    if (!tm.sync(e++, nv, vals, tot, gval, true, ring, true)) return;
+    vals[0] = tot[0] * 0x1p-100;   // the next round depends on this one's totals
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    scal->epoch = e0 + a.epoch_span;
+    scal->team_syncs = (int32_t)(e - e0);
   }
 }
 
@@ -775,37 +863,52 @@ size_t smem_for(size_t elt, const Tiling& t) {
   return sizeof(double) * ((size_t)(t.threads / 64) * NV_MAX + NV_MAX * (MAX_TEAM / 64) + 2) + 3 * ring * elt;
 }
 
-template <typename T, bool PIPE>
+template <typename T, bool PIPE, bool VAR>
 const void* solve_fn_p(const Tiling& t) {
-#define KF_PPT(nt, n) if (t.threads == nt && t.ppt == n) return reinterpret_cast<const void*>(&k_solve<T, nt, n, PIPE>);
+#define KF_PPT(nt, n) if (t.threads == nt && t.ppt == n) return reinterpret_cast<const void*>(&k_solve<T, nt, n, PIPE, VAR>);
   KF_SOLVE_COMBOS
 #undef KF_PPT
   return nullptr;
 }
 
+// kind: bit 0 pipelined CG, bit 1 the instantiation with the variants and the keyframe rule
 template <typename T>
-const void* solve_fn(const Tiling& t, bool pipelined) {
-  return pipelined ? solve_fn_p<T, true>(t) : solve_fn_p<T, false>(t);
+const void* solve_fn(const Tiling& t, int kind) {
+  switch (kind & 3) {
+    case 0: return solve_fn_p<T, false, false>(t);
+    case 1: return solve_fn_p<T, true, false>(t);
+    case 2: return solve_fn_p<T, false, true>(t);
+    default: return solve_fn_p<T, true, true>(t);
+  }
 }
 
-template <typename T, bool PIPE>
+template <typename T, bool PIPE, bool VAR>
 const void* batch_fn_p(int threads, int ppt) {
-#define KF_PPT(nt, n) if (threads == nt && ppt == n) return reinterpret_cast<const void*>(&k_solve_batch<T, nt, n, PIPE>);
+#define KF_PPT(nt, n) if (threads == nt && ppt == n) return reinterpret_cast<const void*>(&k_solve_batch<T, nt, n, PIPE, VAR>);
   KF_SOLVE_COMBOS
 #undef KF_PPT
   return nullptr;
 }
 
-const void* batch_fn(int prec, int threads, int ppt, bool pipelined) {
-  if (prec == KF_F64) return pipelined ? batch_fn_p<double, true>(threads, ppt) : batch_fn_p<double, false>(threads, ppt);
-  return pipelined ? batch_fn_p<float, true>(threads, ppt) : batch_fn_p<float, false>(threads, ppt);
+template <typename T>
+const void* batch_fn_t(int threads, int ppt, int kind) {
+  switch (kind & 3) {
+    case 0: return batch_fn_p<T, false, false>(threads, ppt);
+    case 1: return batch_fn_p<T, true, false>(threads, ppt);
+    case 2: return batch_fn_p<T, false, true>(threads, ppt);
+    default: return batch_fn_p<T, true, true>(threads, ppt);
+  }
+}
+
+const void* batch_fn(int prec, int threads, int ppt, int kind) {
+  return prec == KF_F64 ? batch_fn_t<double>(threads, ppt, kind) : batch_fn_t<float>(threads, ppt, kind);
 }
 
 template <typename T>
-hipError_t solve_t(const Tiling& t, const SolveArgs& a, bool cooperative, bool pipelined, hipStream_t s) {
+hipError_t solve_t(const Tiling& t, const SolveArgs& a, bool cooperative, int kind, hipStream_t s) {
   const size_t sm = smem_for(sizeof(T), t);
   void* args[] = {const_cast<SolveArgs*>(&a)};
-  const void* fn = solve_fn<T>(t, pipelined);
+  const void* fn = solve_fn<T>(t, kind);
   if (!fn) return hipErrorInvalidValue;
   if (sm > 48 * 1024) {
     hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
@@ -834,29 +937,48 @@ int coresident_of(const void* fn, int threads, size_t smem, int device) {
   return per_cu * cus;
 }
 
-int solve_max_coresident(int prec, const Tiling& t, bool pipelined, int device) {
-  const void* fn = prec == KF_F64 ? solve_fn<double>(t, pipelined) : solve_fn<float>(t, pipelined);
+int solve_max_coresident(int prec, const Tiling& t, int kind, int device) {
+  const void* fn = prec == KF_F64 ? solve_fn<double>(t, kind) : solve_fn<float>(t, kind);
   if (!fn) return 0;
   return coresident_of(fn, t.threads, solve_smem_bytes(prec, t), device);
 }
 
-hipError_t launch_solve(int prec, const Tiling& t, const SolveArgs& a, bool cooperative, bool pipelined,
-                        hipStream_t s) {
-  if (prec == KF_F64) return solve_t<double>(t, a, cooperative, pipelined, s);
-  return solve_t<float>(t, a, cooperative, pipelined, s);
+hipError_t launch_solve(int prec, const Tiling& t, const SolveArgs& a, bool cooperative, int kind, hipStream_t s) {
+  if (prec == KF_F64) return solve_t<double>(t, a, cooperative, kind, s);
+  return solve_t<float>(t, a, cooperative, kind, s);
 }
 
-bool solve_batch_supported(int prec, int threads, int ppt) { return batch_fn(prec, threads, ppt, true) != nullptr; }
+hipError_t launch_sync_probe(int prec, const Tiling& t, const SolveArgs& a, int rounds, int nv, hipStream_t s) {
+  const void* fn = nullptr;
+  if (prec == KF_F64) {
+    fn = t.threads == 256 ? reinterpret_cast<const void*>(&k_sync_probe<double, 256>)
+         : t.threads == 512 ? reinterpret_cast<const void*>(&k_sync_probe<double, 512>)
+                            : reinterpret_cast<const void*>(&k_sync_probe<double, 1024>);
+  } else {
+    fn = t.threads == 256 ? reinterpret_cast<const void*>(&k_sync_probe<float, 256>)
+         : t.threads == 512 ? reinterpret_cast<const void*>(&k_sync_probe<float, 512>)
+                            : reinterpret_cast<const void*>(&k_sync_probe<float, 1024>);
+  }
+  const size_t sm = solve_smem_bytes(prec, t);
+  if (sm > 48 * 1024) {
+    hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+    if (err != hipSuccess) return err;
+  }
+  void* args[] = {const_cast<SolveArgs*>(&a), &rounds, &nv};
+  return hipLaunchKernel(fn, dim3(t.blocks), dim3(t.threads), args, (unsigned)sm, s);
+}
 
-int solve_batch_coresident(int prec, int threads, int ppt, bool pipelined, size_t smem, int device) {
-  const void* fn = batch_fn(prec, threads, ppt, pipelined);
+bool solve_batch_supported(int prec, int threads, int ppt) { return batch_fn(prec, threads, ppt, 1) != nullptr; }
+
+int solve_batch_coresident(int prec, int threads, int ppt, int kind, size_t smem, int device) {
+  const void* fn = batch_fn(prec, threads, ppt, kind);
   if (!fn) return 0;
   return coresident_of(fn, threads, smem, device);
 }
 
-hipError_t launch_solve_batch(int prec, int threads, int ppt, bool pipelined, const SolveArgs* tab,
+hipError_t launch_solve_batch(int prec, int threads, int ppt, int kind, const SolveArgs* tab,
                               const int32_t* queue, const int32_t* qoff, int grid, size_t smem, hipStream_t s) {
-  const void* fn = batch_fn(prec, threads, ppt, pipelined);
+  const void* fn = batch_fn(prec, threads, ppt, kind);
   if (!fn || grid < 1) return hipErrorInvalidValue;
   void* args[] = {const_cast<SolveArgs**>(&tab), const_cast<int32_t**>(&queue), const_cast<int32_t**>(&qoff)};
   return hipLaunchKernel(fn, dim3(grid), dim3(threads), args, (unsigned)smem, s);

@@ -31,6 +31,11 @@ KF_F32 = 1
 KF_BF16_F32 = 2
 PRECISIONS = {"f64": KF_F64, "f32": KF_F32, "bf16": KF_BF16_F32}
 
+KF_VARIANT_FULL = 0
+KF_VARIANT_NO_PAIRWISE = 1
+KF_VARIANT_SCALE_POSTFIT = 2
+VARIANTS = {"full": KF_VARIANT_FULL, "no_pairwise": KF_VARIANT_NO_PAIRWISE, "scale_postfit": KF_VARIANT_SCALE_POSTFIT}
+
 KF_PAT_LINE5 = 0
 KF_PAT_SQ5X5 = 1
 PATTERNS = {"line5": KF_PAT_LINE5, "sq5x5": KF_PAT_SQ5X5}
@@ -49,6 +54,7 @@ class KfConfig(ctypes.Structure):
         ("precision", c_int32),
         ("solver_tiles_x", c_int32), ("solver_tiles_y", c_int32),
         ("solver_threads", c_int32), ("solver_cooperative", c_int32), ("pipeline_frames", c_int32),
+        ("variant", c_int32), ("lambda_trans", c_double), ("lambda_inliers", c_int32),
         ("solver_timeout_ms", c_double),
         ("stream", c_void_p), ("workspace", c_void_p), ("workspace_bytes", c_size_t),
     ]
@@ -57,7 +63,7 @@ class KfConfig(ctypes.Structure):
 class KfFrameStats(ctypes.Structure):
     _fields_ = [
         ("n_searched", c_int32), ("n_updated", c_int32), ("n_valid", c_int32), ("cg_iterations", c_int32),
-        ("scale", c_double), ("cg_rel_residual", c_double),
+        ("scale", c_double), ("cg_rel_residual", c_double), ("team_syncs", c_int32), ("new_keyframe", c_int32),
     ]
 
 
@@ -98,6 +104,7 @@ def load_library(path: Optional[str] = None):
         "kf_last_error": (c_char_p, [P]),
         "kf_status_string": (c_char_p, [c_int32]),
         "kf_set_prior": (c_int32, [P, P, P, P, P, P, P, P, dbl16]),
+        "kf_set_prior_network": (c_int32, [P, P, P, P, P, P, P, P, c_int32, c_int32, c_double, dbl16]),
         "kf_stereo_update": (c_int32, [P, P, dbl16]),
         "kf_solve": (c_int32, [P]),
         "kf_fuse_frame": (c_int32, [P, P, dbl16]),
@@ -106,6 +113,7 @@ def load_library(path: Optional[str] = None):
         "kf_export_state": (c_int32, [P, P, P, P, P, POINTER(c_double)]),
         "kf_solver_layout": (c_int32, [P, POINTER(c_int32)]),
         "kf_solve_stream": (c_void_p, [P]),
+        "kf_probe_sync": (c_int32, [P, c_int32, c_int32]),
         "kf_import_state": (c_int32, [P, P, P, P, POINTER(c_double)]),
         "kf_batch_config_default": (None, [POINTER(KfBatchConfig)]),
         "kf_batch_workspace_bytes": (c_size_t, [POINTER(P), c_int32]),
@@ -128,8 +136,9 @@ def load_library(path: Optional[str] = None):
 
 EXPORTED_SYMBOLS = (
     "kf_config_default", "kf_workspace_bytes", "kf_create", "kf_destroy", "kf_last_error", "kf_status_string",
-    "kf_set_prior", "kf_stereo_update", "kf_solve", "kf_fuse_frame", "kf_read_depth", "kf_read_stats",
-    "kf_export_state", "kf_import_state", "kf_solver_layout", "kf_solve_stream",
+    "kf_set_prior", "kf_set_prior_network", "kf_stereo_update", "kf_solve", "kf_fuse_frame", "kf_read_depth",
+    "kf_read_stats",
+    "kf_export_state", "kf_import_state", "kf_solver_layout", "kf_solve_stream", "kf_probe_sync",
     "kf_batch_config_default", "kf_batch_workspace_bytes", "kf_batch_create", "kf_batch_fuse",
     "kf_batch_fuse_subset", "kf_batch_stereo_update", "kf_batch_solve", "kf_batch_layout",
     "kf_batch_last_error", "kf_batch_destroy",
@@ -181,6 +190,13 @@ def kf_destroy(ctx) -> None:
 def kf_set_prior(ctx, image0, logdepth, logdepth_var, grad_x, grad_x_var, grad_y, grad_y_var, T_wc0) -> None:
     _check(load_library().kf_set_prior(ctx, image0, logdepth, logdepth_var, grad_x, grad_x_var, grad_y,
                                        grad_y_var, _pose(T_wc0)), ctx)
+
+
+def kf_set_prior_network(ctx, image0, logdepth, logdepth_var, grad_x, grad_x_var, grad_y, grad_y_var, net_width,
+                         net_height, focal_ref, T_wc0) -> None:
+    _check(load_library().kf_set_prior_network(ctx, image0, logdepth, logdepth_var, grad_x, grad_x_var, grad_y,
+                                               grad_y_var, int(net_width), int(net_height), float(focal_ref),
+                                               _pose(T_wc0)), ctx)
 
 
 def kf_stereo_update(ctx, image1, T_wc1) -> None:
@@ -318,7 +334,8 @@ class Keyframe:
                  huber_delta: float = 1.345, d_near: float = 0.4, d_far: float = 10.0, grad_gate: float = 6.0,
                  sigma_photo: float = 1.0, r_floor: float = 1e-6, K=None, tiles=(0, 0), solver_threads: int = 0,
                  cooperative: bool = False, cg_variant: str = "auto", solver_timeout_ms: float = 0.0,
-                 pipeline_frames: bool = False, stream=None):
+                 pipeline_frames: bool = False, variant: str = "full", lambda_trans: float = 0.0,
+                 lambda_inliers: int = 0, stream=None):
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("Keyframe needs a GPU (the library has no CPU path)")
@@ -337,6 +354,8 @@ class Keyframe:
         cfg.cg_variant = {"auto": 0, "textbook": 1, "pipelined": 2}[cg_variant]
         cfg.solver_timeout_ms = float(solver_timeout_ms)
         cfg.pipeline_frames = int(bool(pipeline_frames))
+        cfg.variant = VARIANTS[variant]
+        cfg.lambda_trans, cfg.lambda_inliers = float(lambda_trans), int(lambda_inliers)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         cfg.stream = c_void_p(self.stream.cuda_stream)
         nbytes = kf_workspace_bytes(cfg)
@@ -384,6 +403,21 @@ class Keyframe:
                      self._map(grad_x_var, "grad_x_var"), self._map(grad_y, "grad_y"),
                      self._map(grad_y_var, "grad_y_var"), T_wc0)
 
+    def set_prior_network(self, image0, logdepth, logdepth_var, grad_x, grad_x_var, grad_y, grad_y_var, T_wc0,
+                          focal_ref: float):
+        """New keyframe from the network's six maps at the network's own size
+        (all of one shape Hn x Wn), resampled and focal-shifted in the library."""
+        torch = _torch()
+        maps = (logdepth, logdepth_var, grad_x, grad_x_var, grad_y, grad_y_var)
+        shape = tuple(logdepth.shape) if isinstance(logdepth, torch.Tensor) else None
+        for name, t in zip(("logdepth", "logdepth_var", "grad_x", "grad_x_var", "grad_y", "grad_y_var"), maps):
+            if not isinstance(t, torch.Tensor) or t.dtype != self.dtype or t.dim() != 2 or tuple(t.shape) != shape \
+                    or not t.is_cuda or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous {self.dtype} CUDA tensor, all six of one 2-D shape")
+        self._keep = (image0, *maps)
+        kf_set_prior_network(self.ctx, self._img(image0, "image0"), *[c_void_p(t.data_ptr()) for t in maps],
+                             shape[1], shape[0], focal_ref, T_wc0)
+
     def _hold(self, image1):
         # the library reads image1 when the stream reaches the call: keep the
         # caching allocator from handing its memory out before then
@@ -419,6 +453,10 @@ class Keyframe:
 
     def stats(self) -> KfFrameStats:
         return kf_read_stats(self.ctx)
+
+    def probe_sync(self, rounds: int, nvalues: int = 2) -> None:
+        """Enqueues the team-synchronisation probe (kf_probe_sync) on the context's stream."""
+        _check(load_library().kf_probe_sync(self.ctx, int(rounds), int(nvalues)), self.ctx)
 
     def export_state(self):
         torch = _torch()

@@ -1,66 +1,152 @@
-"""Float forms against the FP64 oracle on the headline sizes.
+"""Float forms against the FP64 oracle over whole 30-frame sequences.
 
-The precision form (bf16 images and patches, f32 maps and arithmetic, FP64 CG
-inner products) at 640 x 480 with N_s = 128 and the F32 form on a 320 x 240
-sequence with N_s = 64 each run the full per-frame update (stereo + 10 x 20
-pipelined PCG) next to the FP64 oracle (the same 10 x 20 Jacobi PCG,
-iteration-matched) and report the max and RMS depth error, the scale error and
-the rate of pixels whose filter state differs in validity. Stereo decisions
-taken in a different precision can pick a neighbouring sample where two SSDs
-tie; those pixels move the depth locally, which the bounds below allow for.
-Measured on MI355X: precision form 640 x 480, 2 frames: max 8.3e-3, RMS 3.1e-5;
-F32 320 x 240, 4 frames: max 2.7e-2, RMS 1.0e-4; scale equal to 6 digits and
-no validity difference in either. Bounds: relative depth error RMS <= 5e-4 and
-max <= 0.1, scale within 1e-4, at most 0.5 % of the textured pixels with a
-different validity.
+F32 at 320 x 240 (SQ5X5, N_s = 64) and the precision form at 640 x 480 (bf16
+keyframe image, SQ5X5, N_s = 128), both 10 GN x 20 pipelined PCG per frame.
+
+Stage by stage (frames 1, 2, 15 and 30): the GPU's state is exported before the
+frame, after its stereo update and after its solve; the FP64 oracle repeats each
+stage from the GPU's own input state.
+  - stereo: index parity with the FP64 oracle outside the near-tie band of
+    reading R18, at most 0.5 % of the pixels inside it, and the filter values
+    (first observation or Gaussian product) where the indices agree;
+  - solve: the iteration-matched FP64 PCG oracle from the GPU's x, tau and
+    post-stereo filter state, max |dx| <= 2e-4, RMS <= 2e-5, |dtau| <= 2e-5.
+
+End to end (every frame): the GPU and the oracle each run the sequence on
+their own. Their states drift apart through near-tie stereo decisions, which
+move a pixel's measurement by a sample; the per-frame depth error is printed and
+only the index mismatch rate is bounded.
+
+The SQ5X5 search evaluates the keyframe pattern at integer pixels and the new
+frame arrives as uint8, both exact in bf16: the precision form is bit-identical
+to F32 there, which a test checks directly.
 """
 
 import numpy as np
 import pytest
 
 import kfsynth
-from gpu_util import dev, say, torch
-from oracle import OracleKeyframe, SolverParams, StereoParams
+from gpu_util import compare_stereo, dev, np_state, oracle_solve_from, process_pool, r18_eps, rounded_priors, say, \
+    torch
+from oracle import OracleKeyframe, SolverParams, StereoParams, stereo
 
 pytestmark = pytest.mark.gpu
 
+CHECK_FRAMES = (1, 2, 15, 30)
+FORMS = {"c1-f32": (1, "f32", 64), "c2-bf16": (2, "bf16", 128)}
 
-def _run(config, precision, pattern, n_samples, frames):
+
+@pytest.fixture(scope="module")
+def pool():
+    ex = process_pool(8)
+    yield ex
+    ex.shutdown()
+
+
+def _keyframe(case, precision, n_samples, pipeline=False):
     from paper_2207_12244_amd.kf import Keyframe
     t = torch()
-    case = kfsynth.config_case(config, 0, frames=frames)
-    kf = Keyframe(case.W, case.H, precision=precision, pattern=pattern, n_samples=n_samples, n_gn=10, n_cg=20,
-                  K=case.K)
+    kf = Keyframe(case.W, case.H, precision=precision, pattern="sq5x5", n_samples=n_samples, n_gn=10, n_cg=20,
+                  K=case.K, pipeline_frames=pipeline)
     kf.set_prior(dev(case.image0, t.uint8), *[dev(m, t.float32) for m in case.priors.maps()], case.T_wc0)
-    ok = OracleKeyframe(case.K, case.W, case.H, StereoParams(n_samples=n_samples, pattern=pattern),
-                        SolverParams(n_gn=10, n_cg=20, linear_solver="pcg"))
+    return kf
+
+
+_RUNS = {}
+
+
+def _gpu_sequence(form):
+    """Runs the form over its 30 frames once per module: states around the
+    checked frames, and x, match after every frame."""
+    if form in _RUNS:
+        return _RUNS[form]
+    config, precision, ns = FORMS[form]
+    t = torch()
+    case = kfsynth.config_case(config, 0)
+    kf = _keyframe(case, precision, ns)
+    staged, per_frame = {}, []
+    for f in range(1, len(case.images) + 1):
+        img = dev(case.images[f - 1], t.uint8)
+        if f in CHECK_FRAMES:
+            pre = np_state(kf)
+        kf.stereo_update(img, case.poses[f - 1])
+        if f in CHECK_FRAMES:
+            mid = np_state(kf)
+        kf.solve()
+        post = np_state(kf)
+        if f in CHECK_FRAMES:
+            staged[f] = (pre, mid, post)
+        per_frame.append((post["x"].astype(np.float32), post["match"], post["tau"]))
+    kf.close()
+    _RUNS[form] = (case, staged, per_frame)
+    return _RUNS[form]
+
+
+@pytest.mark.parametrize("form", list(FORMS))
+def test_staged_stereo_vs_fp64_oracle(form, pool):
+    config, precision, ns = FORMS[form]
+    say(f"[staged-stereo] {form}: running the GPU sequence")
+    case, staged, _ = _gpu_sequence(form)
+    ok = OracleKeyframe(case.K, case.W, case.H, StereoParams(n_samples=ns, pattern="sq5x5"),
+                        SolverParams(n_gn=10, n_cg=20, linear_solver="pcg"), pool=pool)
     ok.set_prior(case.image0, *case.priors.maps(), case.T_wc0)
-    for f in range(frames):
-        kf.fuse_frame(dev(case.images[f], t.uint8), case.poses[f])
-        ok.fuse_frame(case.images[f], case.poses[f])
-    d, s = kf.read_depth()
-    st = kf.export_state()
-    d_o, s_o = ok.read_depth()
-    rel = np.abs(d.cpu().numpy().astype(np.float64) / d_o - 1.0)
-    valid_gpu = st["var"].cpu().numpy() > 0
-    textured = int(ok.mask.sum())
-    diff_valid = int(np.sum(valid_gpu != ok.valid))
-    say(f"[{precision} {case.W}x{case.H} {frames} frames] depth rel err max {rel.max():.3e} "
-        f"rms {np.sqrt(np.mean(rel ** 2)):.3e}; scale {s:.6f} vs {s_o:.6f}; validity differs at "
-        f"{diff_valid} of {textured} textured pixels")
-    return rel, s, s_o, diff_valid, textured
+    for f in CHECK_FRAMES:
+        pre, mid, _ = staged[f]
+        ok.set_state(rho=pre["rho"], var=pre["var"], valid=pre["var"] > 0)
+        res = ok.search(case.images[f - 1], case.poses[f - 1])
+        compare_stereo(res, pre, mid, r18_eps("f32", 25), (2e-3, 2e-2), f"{form} frame {f}")
 
 
-def _check(rel, s, s_o, diff_valid, textured):
-    assert np.sqrt(np.mean(rel ** 2)) <= 5e-4
-    assert rel.max() <= 0.1
-    assert abs(s / s_o - 1.0) <= 1e-4
-    assert diff_valid <= 0.005 * textured
+@pytest.mark.parametrize("form", list(FORMS))
+def test_staged_solve_vs_fp64_oracle(form):
+    config, precision, ns = FORMS[form]
+    case, staged, _ = _gpu_sequence(form)
+    prior = rounded_priors(case, precision)
+    for f in CHECK_FRAMES:
+        pre, mid, post = staged[f]
+        x_o, tau_o, semi = oracle_solve_from(pre["x"], pre["tau"], prior, mid, 10, 20)
+        err = np.abs(post["x"] - x_o)
+        mx, rms, dt = err.max(), np.sqrt(np.mean(err ** 2)), abs(post["tau"] - tau_o)
+        say(f"[staged-solve] {form} frame {f}: semi {int(semi.valid.sum())} max|dx| {mx:.3e} rms {rms:.3e} "
+            f"dtau {dt:.3e}")
+        assert mx <= 2e-4 and rms <= 2e-5 and dt <= 2e-5, (form, f)
 
 
-def test_precision_form_640x480_vs_fp64_oracle():
-    _check(*_run(2, "bf16", "sq5x5", 128, 2))
+@pytest.mark.parametrize("form", list(FORMS))
+def test_sequence_end_to_end_vs_fp64_oracle(form, pool):
+    """Both sides run all 30 frames on their own; per-frame drift is reported,
+    the index mismatch rate is bounded (near-tie decisions and the drift they
+    cause; at most 2 % of the searched pixels in any frame)."""
+    config, precision, ns = FORMS[form]
+    case, _, per_frame = _gpu_sequence(form)
+    ok = OracleKeyframe(case.K, case.W, case.H, StereoParams(n_samples=ns, pattern="sq5x5"),
+                        SolverParams(n_gn=10, n_cg=20, linear_solver="pcg"), pool=pool)
+    ok.set_prior(case.image0, *case.priors.maps(), case.T_wc0)
+    worst = 0.0
+    for f in range(1, len(case.images) + 1):
+        rep = ok.fuse_frame(case.images[f - 1], case.poses[f - 1])
+        x_g, match_g, tau_g = per_frame[f - 1]
+        rel = np.abs(np.exp(x_g.astype(np.float64) - ok.x) - 1.0)
+        mism = np.count_nonzero(match_g.ravel()[rep.search.pix] != rep.search.k_best)
+        rate = mism / max(1, rep.search.pix.size)
+        worst = max(worst, rate)
+        say(f"[e2e] {form} frame {f:2d}: depth rel err max {rel.max():.3e} rms {np.sqrt(np.mean(rel ** 2)):.3e} "
+            f"scale {np.exp(tau_g):.7f} vs {np.exp(ok.tau):.7f} index mismatches {mism} ({100 * rate:.3f} %)")
+    assert worst <= 0.02
 
 
-def test_f32_sequence_320x240_vs_fp64_oracle():
-    _check(*_run(1, "f32", "sq5x5", 64, 4))
+def test_precision_form_equals_f32_for_sq5x5():
+    """uint8 frames and integer-position keyframe patterns are exact in bf16, so
+    the precision form's SQ5X5 update is bit-identical to F32 (3 frames, 640 x 480)."""
+    t = torch()
+    case = kfsynth.config_case(2, 0, frames=3)
+    outs = []
+    for precision in ("f32", "bf16"):
+        kf = _keyframe(case, precision, 128)
+        for f in range(3):
+            kf.fuse_frame(dev(case.images[f], t.uint8), case.poses[f])
+        outs.append(np_state(kf))
+        kf.close()
+    for k in ("x", "rho", "var", "match"):
+        assert np.array_equal(outs[0][k], outs[1][k]), k
+    assert outs[0]["tau"] == outs[1]["tau"]

@@ -43,67 +43,78 @@ def test_prior_init_mask_and_state(c0, precision):
 
 # ------------------------------------------------------------------ stereo stage
 
-def _compare_search(res, st, margin_eps, rel_tol, label):
-    """Index parity outside the near-tie band, value parity where the index agrees."""
-    match = st["match"].cpu().numpy().ravel()[res.pix]
-    rho = st["rho"].cpu().numpy().astype(np.float64).ravel()[res.pix]
-    var = st["var"].cpu().numpy().astype(np.float64).ravel()[res.pix]
-    has = res.k_best >= 0
-    s = np.sort(np.where(np.isfinite(res.ssd), res.ssd, np.inf), axis=1)
-    best = s[:, 0]
-    with np.errstate(invalid="ignore"):
-        margin = np.where(np.isfinite(s[:, 1]), s[:, 1] - s[:, 0], np.inf)
-    clear = has & (margin >= margin_eps(best))
-    gu.say(f"[{label}] searched {res.pix.size} with-index {has.sum()} clear {clear.sum()} "
-           f"tie-band {(has & ~clear).sum()}")
-    mism_clear = np.count_nonzero(match[clear] != res.k_best[clear])
-    assert mism_clear == 0, f"{mism_clear} index mismatches outside the tie band"
-    # inside the band the GPU's choice must be one of the near-best samples
-    band = np.flatnonzero(has & ~clear)
-    for r in band:
-        k = match[r]
-        assert k >= 0 and res.ssd[r, k] <= best[r] + margin_eps(best[r]), (r, k)
-    assert np.array_equal(match[~has], np.full((~has).sum(), -1))
-    upd = (res.status == UPDATED) & (match == res.k_best)
-    gpu_upd = var > 0
-    same = upd & gpu_upd
-    assert np.count_nonzero(upd & ~gpu_upd) == 0 and np.count_nonzero(gpu_upd & (res.status != UPDATED)) == 0
-    er = np.abs(rho[same] / res.rho_obs[same] - 1)
-    ev = np.abs(var[same] / res.var_obs[same] - 1)
-    gu.say(f"[{label}] updated {same.sum()} rho rel max {er.max():.3e} rms {np.sqrt(np.mean(er**2)):.3e} "
-           f"var rel max {ev.max():.3e}")
-    assert er.max() <= rel_tol[0] and ev.max() <= rel_tol[1]
-    return same
-
-
-def test_stereo_first_frame_f64_line5(c0):
-    gu.say("[stereo] config 0 case 0 f64 line5 N_s=32")
-    kf = gu.make_gpu_kf(c0, "f64", "line5", 32)
+def _stereo_stage(case, precision, pattern, ns, frames=1):
+    """GPU states before and after the stereo update of the last of ``frames``
+    frames (earlier frames fused in full), and the FP64 oracle's search from the
+    GPU's state before it."""
     t = gu.torch()
-    kf.stereo_update(gu.dev(c0.images[0], t.uint8), c0.poses[0])
-    st = kf.export_state()
-    res = gu.first_frame_search(c0, "line5", 32)
-    _compare_search(res, st, lambda b: 1e-9 * (1 + b), (1e-10, 1e-9), "stereo-f64")
-    assert kf.stats().n_updated == int(np.sum(res.status == UPDATED))
+    kf = gu.make_gpu_kf(case, precision, pattern, ns)
+    for f in range(frames - 1):
+        kf.fuse_frame(gu.dev(case.images[f], t.uint8), case.poses[f])
+    pre = gu.np_state(kf)
+    kf.stereo_update(gu.dev(case.images[frames - 1], t.uint8), case.poses[frames - 1])
+    mid = gu.np_state(kf)
+    n_upd = kf.stats().n_updated
+    sp = StereoParams(n_samples=ns, pattern=pattern)
+    res = stereo.epipolar_search(case.image0, case.images[frames - 1], case.K, case.T_wc0, case.poses[frames - 1],
+                                 pre["rho"], pre["var"], pre["var"] > 0, stereo.texture_mask(case.image0), sp)
+    return pre, mid, res, n_upd
+
+
+@pytest.mark.parametrize("pattern", ["line5", "sq5x5"])
+def test_stereo_first_frame_f64(c0, pattern):
+    gu.say(f"[stereo] config 0 case 0 f64 {pattern} N_s=32")
+    pre, mid, res, n_upd = _stereo_stage(c0, "f64", pattern, 32)
+    P = 5 if pattern == "line5" else 25
+    gu.compare_stereo(res, pre, mid, gu.r18_eps("f64", P), (1e-10, 1e-9), f"stereo-f64-{pattern}",
+                      max_band_frac=1e-3)
+    assert n_upd == int(np.sum(res.status == UPDATED))
+
+
+@pytest.mark.parametrize("pattern", ["line5", "sq5x5"])
+def test_stereo_second_frame_f64(pattern):
+    """Second frame: the filter holds estimates, so the search runs over rho +- 2 sqrt(v)
+    and the filter takes the Gaussian product (readings R3, R8)."""
+    case = kfsynth.config_case(0, 0, frames=2)
+    gu.say(f"[stereo] config 0 case 0 f64 {pattern} N_s=32, second frame")
+    pre, mid, res, n_upd = _stereo_stage(case, "f64", pattern, 32, frames=2)
+    P = 5 if pattern == "line5" else 25
+    out = gu.compare_stereo(res, pre, mid, gu.r18_eps("f64", P), (1e-10, 1e-9), f"stereo-f64-{pattern}-frame2",
+                            max_band_frac=1e-3)
+    assert out["filtered"] > 0.5 * out["compared"]      # the product branch is what is being compared
+    assert n_upd == int(np.sum(res.status == UPDATED))
 
 
 @pytest.mark.parametrize("precision", ["f32", "bf16"])
 def test_stereo_first_frame_sq5x5_float(c1_short, precision):
-    """float32 kernels: indices decided in float32 on both sides (R18 band), values vs FP64."""
+    """Float kernels against the FP64 oracle: index parity outside the R18 band."""
     c = c1_short
     gu.say(f"[stereo] config 1 case 0 {precision} sq5x5 N_s=64")
-    kf = gu.make_gpu_kf(c, precision, "sq5x5", 64)
-    t = gu.torch()
-    kf.stereo_update(gu.dev(c.images[0], t.uint8), c.poses[0])
-    st = kf.export_state()
-    res32 = gu.first_frame_search(c, "sq5x5", 64, dtype=np.float32)
-    P = 25
-    same = _compare_search(res32, st, lambda b: 1e-3 * (1 + b) + 0.05 * P, (2e-3, 2e-2), f"stereo-{precision}")
-    res64 = gu.first_frame_search(c, "sq5x5", 64)
-    rho = st["rho"].cpu().numpy().astype(np.float64).ravel()[res64.pix]
-    both = same & (res64.status == UPDATED) & (res64.k_best == res32.k_best)
-    e64 = np.abs(rho[both] / res64.rho_obs[both] - 1)
-    gu.say(f"[stereo-{precision}] vs FP64 oracle: rho rel max {e64.max():.3e} rms {np.sqrt(np.mean(e64**2)):.3e}")
+    pre, mid, res, n_upd = _stereo_stage(c, precision, "sq5x5", 64)
+    gu.compare_stereo(res, pre, mid, gu.r18_eps("f32", 25), (2e-3, 2e-2), f"stereo-{precision}-sq5x5")
+
+
+@pytest.mark.parametrize("size_index", [1, 3])
+@pytest.mark.parametrize("precision", ["f32", "bf16"])
+def test_stereo_line5_float_batched_sizes(precision, size_index):
+    """LINE5, N_s = 32 at the batched workload's sizes (320 x 240, 640 x 480), first
+    and second frame. F32: index parity with the FP64 oracle outside the R18 band.
+    BF16 rounds the interpolated keyframe points (up to half a grey level), which
+    moves SSDs by more than the band: its index mismatch rate against FP64 is
+    reported and bounded (<= 5 %; measured 1.6 % at 320 x 240 and 2.8 % at
+    640 x 480), and the RMS of the inverse-depth error where the decisions agree
+    (<= 2e-2)."""
+    case = kfsynth.config_case(3, 0, frames=2, size_index=size_index)
+    for frames in (1, 2):
+        gu.say(f"[stereo] config 3 {case.W}x{case.H} {precision} line5 N_s=32 frame {frames}")
+        pre, mid, res, _ = _stereo_stage(case, precision, "line5", 32, frames=frames)
+        label = f"stereo-{precision}-line5-{case.W}x{case.H}-frame{frames}"
+        if precision == "f32":
+            gu.compare_stereo(res, pre, mid, gu.r18_eps("f32", 5), (2e-3, 2e-2), label)
+        else:
+            out = gu.compare_stereo(res, pre, mid, gu.r18_eps("f32", 5), None, label, index_parity=False,
+                                    value_rms=2e-2)
+            assert out["mismatch"] <= 0.05 * out["with_index"], out
 
 
 # ------------------------------------------------------------------ solver stage

@@ -1,0 +1,106 @@
+"""The two ablations of Sec. III as solver variants, GPU against the FP64 oracle.
+
+- no_pairwise (Table III): c_net + c_semi only; each depth step is the per-pixel
+  weighted mean, so a Gauss-Newton iteration needs one team synchronisation
+  (the scale step).
+- scale_postfit (Table II): scale-ambiguous log-depth from c_semi + c_grad,
+  then the least-squares fit of the scale to the network log-depth.
+
+Both from the oracle's first-frame filter state (config 0), in FP64 and FP32,
+then a second solve warm started from the first one's (x, tau), and end to end
+(stereo + solve) in FP64.
+"""
+
+import numpy as np
+import pytest
+
+import kfsynth
+from oracle import OracleKeyframe, fusion, stereo
+from oracle.fusion import SolverParams
+from oracle.stereo import StereoParams
+
+import gpu_util as gu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def c0():
+    return kfsynth.config_case(0, 0)
+
+
+def _oracle_state(case):
+    sp = StereoParams(n_samples=32, pattern="line5")
+    z = np.zeros((case.H, case.W))
+    r, v, ok, _ = stereo.stereo_update(case.image0, case.images[0], case.K, case.T_wc0, case.poses[0], z, z,
+                                       np.zeros((case.H, case.W), bool), stereo.texture_mask(case.image0), sp)
+    return np.where(ok, r, 0.0), np.where(ok, v, 0.0)
+
+
+def _kf(case, precision, variant, **kw):
+    from paper_2207_12244_amd.kf import Keyframe
+    t = gu.torch()
+    kf = Keyframe(case.W, case.H, precision=precision, pattern="line5", n_samples=32, K=case.K, variant=variant,
+                  **kw)
+    dt = gu.map_dtype(precision)
+    kf.set_prior(gu.dev(case.image0, t.uint8), *[gu.dev(m, dt) for m in case.priors.maps()], case.T_wc0)
+    return kf
+
+
+CASES = [("no_pairwise", "f64", {}, 1e-12), ("no_pairwise", "f32", {}, 2e-4),
+         ("scale_postfit", "f64", dict(cg_rtol=1e-12, cg_max=4000), 1e-10),
+         ("scale_postfit", "f64", dict(n_cg=20, cg_variant="textbook"), 1e-10),
+         ("scale_postfit", "f64", dict(n_cg=20, cg_variant="pipelined"), 1e-10),
+         ("scale_postfit", "f32", dict(n_cg=20), 2e-4)]
+
+
+@pytest.mark.parametrize("variant,precision,kw,tol", CASES)
+def test_variant_solver_parity(c0, variant, precision, kw, tol):
+    gu.say(f"[variant] config 0 case 0 {variant} {precision} {kw}")
+    rho, var = _oracle_state(c0)
+    dt = gu.np_map_dtype(precision)
+    rho_in, var_in = rho.astype(dt), var.astype(dt)
+    kf = _kf(c0, precision, variant, n_gn=10, **kw)
+    mdt = gu.map_dtype(precision)
+    kf.import_state(rho=gu.dev(rho_in, mdt), var=gu.dev(var_in, mdt))
+    prm = SolverParams(n_gn=10, n_cg=kw.get("n_cg", 20), cg_rtol=kw.get("cg_rtol", 0.0),
+                       cg_max=kw.get("cg_max", 4000), linear_solver="pcg", variant=variant)
+    prior = gu.rounded_priors(c0, precision)
+    semi = gu.oracle_semi(rho_in.astype(np.float64), var_in.astype(np.float64))
+    x_o, tau_o = prior.mu, 0.0
+    for rep in range(2):          # second solve: warm start from the first one's (x, tau)
+        st0 = gu.np_state(kf)
+        kf.solve()
+        st = gu.np_state(kf)
+        s = kf.stats()
+        x_o, tau_o, _ = fusion.gauss_newton(st0["x"], st0["tau"], prior, semi, prm)
+        err = np.abs(st["x"] - x_o)
+        gu.say(f"[variant-{variant}-{precision}] solve {rep + 1}: max|dx| {err.max():.3e} "
+               f"rms {np.sqrt(np.mean(err ** 2)):.3e} dtau {abs(st['tau'] - tau_o):.3e} syncs {s.team_syncs} "
+               f"cg_its {s.cg_iterations}")
+        assert err.max() <= tol and abs(st["tau"] - tau_o) <= tol
+        if precision != "f64":
+            assert np.sqrt(np.mean(err ** 2)) <= 2e-5
+        if variant == "no_pairwise":
+            assert s.team_syncs == 10 and s.cg_iterations == 0
+    if variant == "scale_postfit":
+        # the fitted scale is the mean offset of the network log-depth from y = x - tau
+        assert abs(np.mean(prior.mu - (st["x"] - st["tau"])) - st["tau"]) <= (1e-12 if precision == "f64" else 1e-5)
+
+
+@pytest.mark.parametrize("variant", ["no_pairwise", "scale_postfit"])
+def test_variant_end_to_end_f64(c0, variant):
+    """Stereo + variant solve in one kf_fuse_frame against the oracle keyframe."""
+    gu.say(f"[variant-e2e] config 0 case 0 f64 {variant}")
+    t = gu.torch()
+    kf = _kf(c0, "f64", variant, n_gn=10, cg_rtol=1e-12, cg_max=4000)
+    kf.fuse_frame(gu.dev(c0.images[0], t.uint8), c0.poses[0])
+    d, s = kf.read_depth()
+    ok = OracleKeyframe(c0.K, c0.W, c0.H, StereoParams(n_samples=32, pattern="line5"),
+                        SolverParams(n_gn=10, cg_rtol=1e-12, cg_max=4000, linear_solver="pcg", variant=variant))
+    ok.set_prior(c0.image0, *c0.priors.maps(), c0.T_wc0)
+    ok.fuse_frame(c0.images[0], c0.poses[0])
+    d_o, s_o = ok.read_depth()
+    err = np.abs(np.log(d.cpu().numpy()) - np.log(d_o))
+    gu.say(f"[variant-e2e-{variant}] max|dlogd| {err.max():.3e} scale {s:.12f} vs {s_o:.12f}")
+    assert err.max() <= 1e-9 and abs(np.log(s / s_o)) <= 1e-9

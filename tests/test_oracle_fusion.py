@@ -297,3 +297,76 @@ def test_gauss_newton_cost_decreases():
     x, tau, info = fusion.gauss_newton(prior.mu, 0.0, prior, semi, SolverParams(n_gn=10, linear_solver="direct"))
     costs = [c0] + info.costs
     assert all(b <= a * (1 + 1e-12) for a, b in zip(costs, costs[1:]))
+
+
+# ------------------------------------------------------------------ ablation variants (Sec. III)
+
+def _no_grad(prior):
+    return PriorMaps(prior.mu, prior.var_n, prior.gx, np.full_like(prior.var_gx, np.inf), prior.gy,
+                     np.full_like(prior.var_gy, np.inf))
+
+
+def _no_net(prior):
+    return PriorMaps(prior.mu, np.full_like(prior.var_n, np.inf), prior.gx, prior.var_gx, prior.gy, prior.var_gy)
+
+
+@pytest.mark.parametrize("delta", [DELTA, np.inf])
+def test_no_pairwise_variant_equals_full_scheme_without_gradient_terms(delta):
+    """Table III variant: its closed-form x-steps equal the full scheme's sparse
+    solves on the same problem with the gradient terms removed (infinite gradient
+    variances: zero edge weights), iteration by iteration. A gradient term left in
+    the variant, or a wrong weight in its weighted mean, fails."""
+    prior, semi, _ = _problem(8, 11, seed=21)
+    x0 = prior.mu + 0.02
+    a = fusion.gauss_newton(x0, 0.1, prior, semi, SolverParams(n_gn=6, huber_delta=delta, variant="no_pairwise"))
+    b = fusion.gauss_newton(x0, 0.1, _no_grad(prior), semi, SolverParams(n_gn=6, huber_delta=delta,
+                                                                          linear_solver="direct"))
+    assert np.max(np.abs(a[0] - b[0])) <= 1e-12 and abs(a[1] - b[1]) <= 1e-12
+
+
+def test_no_pairwise_variant_converges_to_the_minimiser_without_gradient_terms():
+    """Iterated to convergence the variant reaches the unique minimiser of
+    c_net + c_semi (joint IRLS + Newton polish, an independent solver)."""
+    prior, semi, _ = _problem(7, 9, seed=22)
+    xm, tm = fusion.minimiser(_no_grad(prior), semi, DELTA)
+    x, tau, _ = fusion.gauss_newton(prior.mu, 0.0, prior, semi, SolverParams(n_gn=400, variant="no_pairwise"))
+    assert np.max(np.abs(x - xm)) <= 1e-9 and abs(tau - tm) <= 1e-9
+
+
+@pytest.mark.parametrize("delta", [DELTA, np.inf])
+def test_scale_postfit_noiseless_recovers_truth(delta):
+    """Table II variant on noiseless consistent input (mu = x_true, g = D x_true,
+    z = x_true - tau_true): the scale-ambiguous solve gives y = x_true - tau_true
+    and the least-squares fit tau = tau_true, so x = x_true."""
+    prior, semi, xt = _problem(9, 12, seed=23, noiseless=True, tau_true=0.4)
+    x, tau, _ = fusion.gauss_newton(prior.mu + 0.05, 0.0, prior, semi,
+                                    SolverParams(n_gn=3, huber_delta=delta, linear_solver="direct",
+                                                 variant="scale_postfit"))
+    assert np.max(np.abs(x - xt)) <= 1e-10 and abs(tau - 0.4) <= 1e-10
+
+
+def test_scale_postfit_ignores_the_network_depth_until_the_fit():
+    """The scale-ambiguous log-depth y = x - tau does not depend on the network's
+    log-depth at all; replacing mu moves only tau, by the mean of the change.
+    A network term left in the scale-ambiguous solve fails."""
+    prior, semi, _ = _problem(8, 10, seed=24)
+    prm = SolverParams(n_gn=5, linear_solver="direct", variant="scale_postfit")
+    x1, t1, _ = fusion.gauss_newton(prior.mu, 0.0, prior, semi, prm)
+    rng = np.random.default_rng(5)
+    dmu = rng.normal(0.0, 0.3, prior.mu.shape)
+    p2 = PriorMaps(prior.mu + dmu, prior.var_n, prior.gx, prior.var_gx, prior.gy, prior.var_gy)
+    x2, t2, _ = fusion.gauss_newton(prior.mu, 0.0, p2, semi, prm)
+    assert np.max(np.abs((x2 - t2) - (x1 - t1))) <= 1e-12
+    assert abs((t2 - t1) - float(np.mean(dmu))) <= 1e-12
+
+
+def test_scale_postfit_solve_is_stationary_for_semi_and_gradient_terms():
+    """Iterated to convergence, y zeroes the gradient of c_semi + c_grad at tau = 0
+    (differentiated term by term, the network term removed)."""
+    prior, semi, _ = _problem(7, 9, seed=25)
+    x, tau, _ = fusion.gauss_newton(prior.mu, 0.0, prior, semi,
+                                    SolverParams(n_gn=300, linear_solver="direct", variant="scale_postfit"))
+    y = x - tau
+    g0, _ = fusion.cost_gradient(prior.mu, 0.0, _no_net(prior), semi, DELTA)
+    g, _ = fusion.cost_gradient(y, 0.0, _no_net(prior), semi, DELTA)
+    assert np.sqrt(np.sum(g * g)) <= 1e-9 * np.sqrt(np.sum(g0 * g0))

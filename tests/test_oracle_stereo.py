@@ -356,3 +356,60 @@ def test_subpixel_step_direction_on_an_asymmetric_ramp(pattern, P):
     d_a, d_b = 8.0 / 6.0, 8.0 / 7.0
     assert np.allclose(res.d_star[sel], d_a + 0.25 * (d_b - d_a), rtol=1e-15, atol=0)
     assert np.allclose(res.var_d[sel], (d_b - d_a) ** 2 / (64.0 * P), rtol=1e-13, atol=0)
+
+
+def test_search_in_row_blocks_equals_one_call(case_c0):
+    """Searching the texture mask in row blocks (another executor, as the GPU
+    comparisons do with a process pool) concatenates to exactly the one-call
+    result, first frame and with a filter state; each block's pixels are searched
+    by the same function on the whole images."""
+    import concurrent.futures
+    from oracle.pipeline import search_in_blocks
+    c = case_c0
+    sp = StereoParams(n_samples=32, pattern="sq5x5")
+    mask = stereo.texture_mask(c.image0)
+    z = np.zeros((c.H, c.W))
+    args = (c.image0, c.images[0], c.K, c.T_wc0, c.poses[0], z, z, np.zeros((c.H, c.W), bool), mask, sp)
+    one = stereo.epipolar_search(*args)
+    with concurrent.futures.ThreadPoolExecutor(3) as ex:
+        blk = search_in_blocks(ex, 5, *args)
+        r, v, ok = stereo.filter_update(z, z, np.zeros((c.H, c.W), bool), one.pix[one.status == UPDATED],
+                                        one.rho_obs[one.status == UPDATED], one.var_obs[one.status == UPDATED])
+        args2 = (c.image0, c.images[0], c.K, c.T_wc0, c.poses[0], r, v, ok, mask, sp)
+        one2 = stereo.epipolar_search(*args2)
+        blk2 = search_in_blocks(ex, 7, *args2)
+    for a, b in ((one, blk), (one2, blk2)):
+        for f in stereo.SearchResult.__dataclass_fields__:
+            assert np.array_equal(getattr(a, f), getattr(b, f)), f
+
+
+def test_keyframe_decision_rule():
+    """Sec. II keyframe rule: translation beyond lambda_trans or inliers below
+    lambda_inliers ask for a new keyframe; strict comparisons; 0 disables a test.
+    The translation is the distance between camera centres, whatever the
+    rotations (a rotation about the keyframe centre moves nothing)."""
+    from oracle.pipeline import NEW_KF_INLIERS, NEW_KF_TRANSLATION, camera_translation, keyframe_decision
+    R = kfsynth.so3_exp(np.array([0.3, -0.2, 0.5]))
+    T0 = kfsynth.pose_matrix(R, np.array([1.0, 2.0, 3.0]))
+    T1 = kfsynth.pose_matrix(R.T, np.array([1.0, 2.0, 3.0]) + np.array([0.03, -0.04, 0.0]))
+    assert abs(camera_translation(T0, T1) - 0.05) < 1e-15
+    assert camera_translation(T0, kfsynth.pose_matrix(np.eye(3), T0[:3, 3])) == 0.0
+    assert keyframe_decision(0.05, 100, 0.05, 100) == 0
+    assert keyframe_decision(0.0500001, 100, 0.05, 100) == NEW_KF_TRANSLATION
+    assert keyframe_decision(0.05, 99, 0.05, 100) == NEW_KF_INLIERS
+    assert keyframe_decision(1.0, 0, 0.5, 1) == NEW_KF_TRANSLATION | NEW_KF_INLIERS
+    assert keyframe_decision(1e9, 0, 0.0, 0) == 0
+
+
+def test_oracle_keyframe_skips_fusion_on_a_new_keyframe(case_c0):
+    """When the rule fires, the semi-dense filter is updated but the depth map
+    keeps its last fused state."""
+    from oracle import OracleKeyframe, SolverParams
+    from oracle.pipeline import NEW_KF_INLIERS
+    c = case_c0
+    ok = OracleKeyframe(c.K, c.W, c.H, StereoParams(n_samples=32, pattern="line5"),
+                        SolverParams(n_gn=2, linear_solver="direct"), lambda_inliers=10 ** 9)
+    ok.set_prior(c.image0, *c.priors.maps(), c.T_wc0)
+    rep = ok.fuse_frame(c.images[0], c.poses[0])
+    assert rep.new_keyframe == NEW_KF_INLIERS and rep.n_updated > 0 and ok.valid.sum() == rep.n_updated
+    assert np.array_equal(ok.x, c.priors.logdepth) and ok.tau == 0.0
