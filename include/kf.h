@@ -229,6 +229,20 @@ kf_status kf_fuse_frame(kf_ctx* ctx, const uint8_t* image1, const double T_wc1[1
    kf_set_prior. */
 kf_status kf_read_depth(kf_ctx* ctx, void* depth_out, void* var_out, double* scale_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, serving loops and harnesses that forbid allocation): kf_fuse_frame
+   with the same results, whose kernels take their scratch -- the staged new
+   frame and the solver team's exchange words -- from a fixed array inside the
+   library (4 MiB per device, held until the process ends) instead of the
+   context's workspace. Allocates nothing and calls no allocating routine.
+   KF_ERR_ARG if the keyframe needs more scratch than the array holds
+   ((height + 1) x row stride of the staged frame, rows padded to a multiple of
+   64 bytes >= width + 8, plus the exchange words: 640 x 480 needs 1.7 MB);
+   KF_ERR_STATE before kf_set_prior or with pipeline_frames. Every call on a
+   device shares that device's array and clears what must start at zero, so
+   calls that overlap on one device (contexts on different streams) race. */
+kf_status kf_fuse_frame_static(kf_ctx* ctx, const uint8_t* image1, const double T_wc1[16]);
+
 /* Statistics of the last stereo update and solve (host struct). Synchronises. */
 kf_status kf_read_stats(kf_ctx* ctx, kf_frame_stats* out);
 

@@ -2,6 +2,7 @@
 // per-frame epipolar constants (host FP64) and kernel launches.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -364,6 +365,39 @@ hipError_t epoch_wrap_if_needed(kf_ctx* c, uint32_t bound) {
 
 namespace {
 
+// Scratch of kf_fuse_frame_static: the staged frame and the solver team's
+// exchange words live here instead of the context's workspace. Each device
+// holds its own copy for the life of the process; host code uses only the
+// per-device address that hipGetSymbolAddress returns, never the symbol.
+constexpr size_t KF_STATIC_SCRATCH_BYTES = (size_t)4 << 20;
+static __device__ __align__(256) unsigned char scratch[KF_STATIC_SCRATCH_BYTES];
+
+constexpr int KF_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[KF_MAX_DEVICES] = {};
+
+// Device address of `scratch` on `device`, looked up once per device with
+// that device current.
+hipError_t static_scratch(int device, char** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (device < 0 || device >= KF_MAX_DEVICES) return hipErrorInvalidDevice;
+  if (!g_scratch_ptr[device]) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e == hipSuccess && cur != device) e = hipSetDevice(device);
+    void* p = nullptr;
+    if (e == hipSuccess) e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur >= 0 && cur != device) {
+      const hipError_t e2 = hipSetDevice(cur);
+      if (e == hipSuccess) e = e2;
+    }
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = static_cast<char*>(p);
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
+
 kf_status check_device_flags(kf_ctx* c) {
   DevScalars h;
   hipError_t e = hipMemcpyAsync(&h, scal_ptr(c), sizeof(h), hipMemcpyDeviceToHost, c->stream);
@@ -684,6 +718,48 @@ kf_status kf_read_stats(kf_ctx* c, kf_frame_stats* out) {
   out->new_keyframe = h.new_keyframe;
   if (h.err & ERR_TIMEOUT) return fail(c, KF_ERR_TIMEOUT, "solver workgroups timed out waiting for their team");
   if (h.err & ERR_INPUT) return fail(c, KF_ERR_INPUT, "device found a non-finite input or a variance <= 0");
+  return KF_OK;
+}
+
+kf_status kf_fuse_frame_static(kf_ctx* c, const uint8_t* image1, const double T_wc1[16]) {
+  if (!c) return KF_ERR_ARG;
+  if (!c->has_prior) return fail(c, KF_ERR_STATE, "kf_fuse_frame_static before kf_set_prior");
+  if (c->cfg.pipeline_frames) return fail(c, KF_ERR_STATE, "kf_fuse_frame_static needs a context without pipeline_frames");
+  if (!image1) return fail(c, KF_ERR_ARG, "kf_fuse_frame_static: NULL image");
+  if (!pose_ok(T_wc1)) return fail(c, KF_ERR_ARG, "kf_fuse_frame_static: pose must be finite with last row 0 0 0 1");
+  const size_t stage = align256((size_t)(c->cfg.height + 1) * stage_stride(c->cfg.width));
+  const size_t exch = c->lay.total - c->lay.parts;   // exchange words of the solver team
+  if (stage + exch > KF_STATIC_SCRATCH_BYTES)
+    return fail(c, KF_ERR_ARG, "kf_fuse_frame_static: this keyframe needs " + std::to_string(stage + exch) +
+                                   " bytes of scratch, the static array holds " +
+                                   std::to_string(KF_STATIC_SCRATCH_BYTES));
+  char* base = nullptr;
+  hipError_t e = static_scratch(c->device, &base);
+  if (e != hipSuccess) return hip_fail(c, e, "kf_fuse_frame_static (static scratch address)");
+  StereoArgs a;
+  if (!stereo_args(c, image1, T_wc1, &a)) return fail(c, KF_ERR_ARG, "kf_fuse_frame_static: singular pose");
+  a.i1s = reinterpret_cast<uint8_t*>(base);
+  const kf_config& g = c->cfg;
+  const uint32_t bound = solve_epoch_bound(g);
+  e = epoch_wrap_if_needed(c, bound);
+  // the array holds whatever the last call on this device left: its exchange
+  // words start from zero (epoch 0 is never used), cleared by a fill kernel
+  if (e == hipSuccess) e = launch_zero(base + stage, exch, c->stream);
+  if (e == hipSuccess) e = launch_stereo(g.precision, g.pattern, g.n_samples, a, c->stereo_blocks, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "kf_fuse_frame_static (stereo)");
+  ++c->frame;
+  SolveArgs sa;
+  solve_args(c, &sa);
+  sa.parts = reinterpret_cast<uint64_t*>(base + stage);
+  sa.halo = reinterpret_cast<uint64_t*>(base + stage + (c->lay.halo - c->lay.parts));
+  const int kind = solve_kind(g);
+  if (c->coresident < 0) c->coresident = solve_max_coresident(g.precision, c->tiling, kind, c->device);
+  if (c->coresident < c->tiling.blocks)
+    return fail(c, KF_ERR_ARG, "solver tiling needs " + std::to_string(c->tiling.blocks) +
+                               " co-resident workgroups, the device holds " + std::to_string(c->coresident));
+  e = launch_solve(g.precision, c->tiling, sa, g.solver_cooperative != 0, kind, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "kf_fuse_frame_static (solve)");
+  c->epoch += bound;
   return KF_OK;
 }
 

@@ -108,6 +108,7 @@ def load_library(path: Optional[str] = None):
         "kf_stereo_update": (c_int32, [P, P, dbl16]),
         "kf_solve": (c_int32, [P]),
         "kf_fuse_frame": (c_int32, [P, P, dbl16]),
+        "kf_fuse_frame_static": (c_int32, [P, P, dbl16]),
         "kf_read_depth": (c_int32, [P, P, P, POINTER(c_double)]),
         "kf_read_stats": (c_int32, [P, POINTER(KfFrameStats)]),
         "kf_export_state": (c_int32, [P, P, P, P, P, POINTER(c_double)]),
@@ -136,7 +137,7 @@ def load_library(path: Optional[str] = None):
 
 EXPORTED_SYMBOLS = (
     "kf_config_default", "kf_workspace_bytes", "kf_create", "kf_destroy", "kf_last_error", "kf_status_string",
-    "kf_set_prior", "kf_set_prior_network", "kf_stereo_update", "kf_solve", "kf_fuse_frame", "kf_read_depth",
+    "kf_set_prior", "kf_set_prior_network", "kf_stereo_update", "kf_solve", "kf_fuse_frame", "kf_fuse_frame_static", "kf_read_depth",
     "kf_read_stats",
     "kf_export_state", "kf_import_state", "kf_solver_layout", "kf_solve_stream", "kf_probe_sync",
     "kf_batch_config_default", "kf_batch_workspace_bytes", "kf_batch_create", "kf_batch_fuse",
