@@ -78,6 +78,15 @@ typedef enum {
                                    gradient variances must be finite */
 } kf_variant;
 
+/* Robust cost on every term's whitened residual r (Sec. II-C uses Huber; Sec. V
+   names Tukey's biweight as the alternative to try). Both use huber_delta as the
+   threshold c. */
+typedef enum {
+  KF_ROBUST_HUBER = 0,   /* IRLS weight min(1, c / |r|) */
+  KF_ROBUST_TUKEY = 1    /* IRLS weight (1 - (r/c)^2)^2 for |r| <= c, 0 beyond (non-convex: a term far
+                            off is ignored; a pixel whose every term is ignored keeps its value) */
+} kf_robust;
+
 /* Matching pattern of the epipolar search (Sec. II-B). */
 typedef enum {
   KF_PAT_LINE5 = 0, /* five points, 1 px apart, along the epipolar lines of both images */
@@ -96,7 +105,8 @@ typedef struct {
   int32_t cg_variant;           /* 0 automatic (pipelined when cg_rtol == 0), 1 textbook PCG,
                                    2 pipelined PCG: same iterates in exact arithmetic, one team
                                    synchronisation per iteration instead of two */
-  double huber_delta;           /* Huber threshold on whitened residuals (> 0, may be INFINITY) */
+  double huber_delta;           /* threshold c of the robust cost on whitened residuals (> 0; INFINITY
+                                   gives plain least squares with Huber) */
   double d_near, d_far;         /* depth range of a full-line search, 0 < d_near < d_far */
   double grad_gate;             /* texture gate: |grad I0| >= grad_gate grey levels per pixel */
   double sigma_photo;           /* photometric noise (grey levels) in eq. (semi), > 0 */
@@ -112,6 +122,7 @@ typedef struct {
                                    current frame's solve (same results); 0: one stream. A context with
                                    1 cannot join a batch. */
   int32_t variant;              /* kf_variant (default KF_VARIANT_FULL) */
+  int32_t robust;               /* kf_robust (default KF_ROBUST_HUBER) */
   double lambda_trans;          /* Sec. II keyframe rule: a frame whose camera centre is more than
                                    lambda_trans (pose units) from the keyframe's asks for a new
                                    keyframe; 0 disables the test */

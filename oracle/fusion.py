@@ -9,7 +9,12 @@ tau = ln s (readings R16, R12):
               + sum_{v<H-1} H((x_{i+W} - x_i - g_y,i) / sigma_gy,i)
 
 H(r) = r^2 for |r| <= delta, 2 delta |r| - delta^2 beyond (Huber, equal to the
-paper's r^T R^-1 r inside the quadratic zone). Every residual is affine in
+paper's r^T R^-1 r inside the quadratic zone). Tukey's biweight, which the paper
+names as the alternative to try (Sec. V), is the other robust cost available
+(``SolverParams.robust``, reading R26): T(r) = (c^2/3) (1 - (1 - (r/c)^2)^3) for
+|r| <= c and c^2/3 beyond, normalised like H so that T(r) ~ r^2 for small r; its
+IRLS weight T'(r) / (2 r) = (1 - (r/c)^2)^2 inside and 0 beyond. T is not convex:
+the uniqueness statements below are Huber's. Every residual is affine in
 (x, tau), so c is convex, and strictly convex in x because every pixel has a
 network term.
 
@@ -71,6 +76,7 @@ class SolverParams:
     huber_delta: float = 1.345
     linear_solver: str = "pcg"   # "pcg" or "direct"
     variant: str = "full"        # "full" (Sec. II-C), "no_pairwise" (Table III), "scale_postfit" (Table II)
+    robust: str = "huber"        # "huber" (Sec. II-C) or "tukey" (Sec. V); threshold huber_delta either way
 
 
 # ---------------------------------------------------------------- Huber
@@ -97,6 +103,36 @@ def huber_weight(r, delta):
         return np.where(a <= delta, 1.0, delta / a)
 
 
+def tukey(r, c):
+    """Tukey's biweight, normalised to r^2 near zero: (c^2/3)(1 - (1 - (r/c)^2)^3), c^2/3 beyond c."""
+    t2 = (np.asarray(r) / c) ** 2
+    return np.where(t2 <= 1.0, (c * c / 3.0) * (1.0 - (1.0 - t2) ** 3), c * c / 3.0)
+
+
+def tukey_derivative(r, c):
+    r = np.asarray(r)
+    t2 = (r / c) ** 2
+    return np.where(t2 <= 1.0, 2.0 * r * (1.0 - t2) ** 2, 0.0)
+
+
+def tukey_weight(r, c):
+    """IRLS weight T'(r) / (2 r) = (1 - (r/c)^2)^2 inside c, 0 beyond."""
+    t2 = (np.asarray(r) / c) ** 2
+    return np.where(t2 <= 1.0, (1.0 - t2) ** 2, 0.0)
+
+
+def robust_cost(r, delta, robust="huber"):
+    return huber(r, delta) if robust == "huber" else tukey(r, delta)
+
+
+def robust_derivative(r, delta, robust="huber"):
+    return huber_derivative(r, delta) if robust == "huber" else tukey_derivative(r, delta)
+
+
+def robust_weight(r, delta, robust="huber"):
+    return huber_weight(r, delta) if robust == "huber" else tukey_weight(r, delta)
+
+
 # ---------------------------------------------------------------- residuals, cost
 
 def residuals(x, tau, prior: PriorMaps, semi: SemiMeasurements):
@@ -112,19 +148,20 @@ def _sd(var):
     return np.sqrt(var)
 
 
-def cost(x, tau, prior: PriorMaps, semi: SemiMeasurements, delta) -> float:
+def cost(x, tau, prior: PriorMaps, semi: SemiMeasurements, delta, robust="huber") -> float:
     r_net, r_semi, r_gx, r_gy = residuals(x, tau, prior, semi)
     S = semi.valid
-    c = np.sum(huber(r_net / _sd(prior.var_n), delta))
+    c = np.sum(robust_cost(r_net / _sd(prior.var_n), delta, robust))
     if np.any(S):
-        c += np.sum(huber(r_semi[S] / _sd(semi.R[S]), delta))
-    c += np.sum(huber(r_gx / _sd(prior.var_gx[:, :-1]), delta))
-    c += np.sum(huber(r_gy / _sd(prior.var_gy[:-1, :]), delta))
+        c += np.sum(robust_cost(r_semi[S] / _sd(semi.R[S]), delta, robust))
+    c += np.sum(robust_cost(r_gx / _sd(prior.var_gx[:, :-1]), delta, robust))
+    c += np.sum(robust_cost(r_gy / _sd(prior.var_gy[:-1, :]), delta, robust))
     return float(c)
 
 
-def cost_gradient(x, tau, prior: PriorMaps, semi: SemiMeasurements, delta):
+def cost_gradient(x, tau, prior: PriorMaps, semi: SemiMeasurements, delta, robust="huber"):
     """(dc/dx, dc/dtau), by differentiating each term directly (no normal equations)."""
+    huber_derivative = lambda r, d: robust_derivative(r, d, robust)   # noqa: E731
     r_net, r_semi, r_gx, r_gy = residuals(x, tau, prior, semi)
     S = semi.valid
     sn = _sd(prior.var_n)
@@ -148,8 +185,9 @@ def cost_gradient(x, tau, prior: PriorMaps, semi: SemiMeasurements, delta):
 
 # ---------------------------------------------------------------- normal equations
 
-def irls_weights(x, tau, prior: PriorMaps, semi: SemiMeasurements, delta):
-    """Per-term weights h(r/sigma)/sigma^2 at (x, tau) (reading R12)."""
+def irls_weights(x, tau, prior: PriorMaps, semi: SemiMeasurements, delta, robust="huber"):
+    """Per-term weights h(r/sigma)/sigma^2 at (x, tau) (readings R12, R26)."""
+    huber_weight = lambda r, d: robust_weight(r, d, robust)   # noqa: E731
     r_net, r_semi, r_gx, r_gy = residuals(x, tau, prior, semi)
     w_n = huber_weight(r_net / _sd(prior.var_n), delta) / prior.var_n
     S = semi.valid
@@ -218,9 +256,12 @@ def pcg(A, b, x0, n_iter: int, rtol: float = 0.0, max_iter: int = 4000):
     Returns (x, iterations done).
     """
     d = A.diagonal()
+    # a row whose every term has zero weight (possible with Tukey's cost) keeps
+    # its value: its preconditioned residual is taken as 0
+    dinv = np.divide(1.0, d, out=np.zeros_like(d), where=d > 0)
     x = np.array(x0, dtype=np.float64, copy=True)
     r = b - A @ x
-    z = r / d
+    z = r * dinv
     p = z.copy()
     rz = float(r @ z)
     bnorm = float(np.sqrt(b @ b))
@@ -236,7 +277,7 @@ def pcg(A, b, x0, n_iter: int, rtol: float = 0.0, max_iter: int = 4000):
         x += alpha * p
         r -= alpha * q
         it += 1
-        z = r / d
+        z = r * dinv
         rz_new = float(r @ z)
         if rtol > 0 and np.sqrt(r @ r) <= rtol * bnorm:
             break
@@ -250,13 +291,16 @@ def pcg(A, b, x0, n_iter: int, rtol: float = 0.0, max_iter: int = 4000):
 
 # ---------------------------------------------------------------- Gauss-Newton
 
-def scale_step(x, tau, semi: SemiMeasurements, delta):
-    """Closed-form tau with the semi weights at (x, tau): sum w (x - z) / sum w (R13)."""
+def scale_step(x, tau, semi: SemiMeasurements, delta, robust="huber"):
+    """Closed-form tau with the semi weights at (x, tau): sum w (x - z) / sum w (R13);
+    unchanged when no semi-dense term has weight."""
     S = semi.valid
     if not np.any(S):
         return tau
     r = (x[S] - tau - semi.z[S]) / np.sqrt(semi.R[S])
-    w = huber_weight(r, delta) / semi.R[S]
+    w = robust_weight(r, delta, robust) / semi.R[S]
+    if not np.sum(w) > 0.0:
+        return tau
     return float(np.sum(w * (x[S] - semi.z[S])) / np.sum(w))
 
 
@@ -278,13 +322,15 @@ def gauss_newton(x0, tau0, prior: PriorMaps, semi: SemiMeasurements, params: Sol
     x = np.array(x0, dtype=np.float64, copy=True)
     tau = float(tau0)
     info = GNInfo()
+    rb = params.robust
     for _ in range(params.n_gn):
-        w_n, w_s, c_x, c_y = irls_weights(x, tau, prior, semi, delta)
+        w_n, w_s, c_x, c_y = irls_weights(x, tau, prior, semi, delta, rb)
         if params.variant == "no_pairwise":
             # Table III: no gradient terms, so A is diagonal and the x-step is
             # the per-pixel weighted mean of the two log-depth estimates
             z = np.where(semi.valid, semi.z, 0.0)
-            x = (w_n * prior.mu + w_s * (tau + z)) / (w_n + w_s)
+            wsum = w_n + w_s
+            x = np.where(wsum > 0, (w_n * prior.mu + w_s * (tau + z)) / np.where(wsum > 0, wsum, 1.0), x)
             its = 0
         else:
             A, b = normal_equations(w_n, w_s, c_x, c_y, tau, prior, semi)
@@ -294,9 +340,9 @@ def gauss_newton(x0, tau0, prior: PriorMaps, semi: SemiMeasurements, params: Sol
             else:
                 xv, its = pcg(A, b, x.ravel(), params.n_cg, params.cg_rtol, params.cg_max)
             x = xv.reshape(H, W)
-        tau = scale_step(x, tau, semi, delta)
+        tau = scale_step(x, tau, semi, delta, rb)
         info.cg_iterations.append(its)
-        info.costs.append(cost(x, tau, prior, semi, delta))
+        info.costs.append(cost(x, tau, prior, semi, delta, rb))
     return x, tau, info
 
 
@@ -312,7 +358,7 @@ def scale_postfit(x0, tau0, prior: PriorMaps, semi: SemiMeasurements, params: So
     info = GNInfo()
     zeros = np.zeros((H, W))
     for _ in range(params.n_gn):
-        _, w_s, c_x, c_y = irls_weights(y, 0.0, prior, semi, delta)
+        _, w_s, c_x, c_y = irls_weights(y, 0.0, prior, semi, delta, params.robust)
         A, b = normal_equations(zeros, w_s, c_x, c_y, 0.0, prior, semi)   # no network term
         if params.linear_solver == "direct":
             yv = solve_direct(A, b)

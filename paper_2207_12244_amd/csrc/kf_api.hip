@@ -48,6 +48,8 @@ const char* validate(const kf_config& c) {
   if (c.pipeline_frames != 0 && c.pipeline_frames != 1) return "pipeline_frames must be 0 or 1";
   if (c.cg_variant < 0 || c.cg_variant > 2) return "cg_variant must be 0, 1 or 2";
   if (c.variant < KF_VARIANT_FULL || c.variant > KF_VARIANT_SCALE_POSTFIT) return "unknown variant";
+  if (c.robust != KF_ROBUST_HUBER && c.robust != KF_ROBUST_TUKEY) return "unknown robust cost";
+  if (c.robust == KF_ROBUST_TUKEY && !std::isfinite(c.huber_delta)) return "Tukey's threshold must be finite";
   if (!(c.lambda_trans >= 0.0) || !std::isfinite(c.lambda_trans)) return "lambda_trans must be finite and >= 0";
   if (c.lambda_inliers < 0) return "lambda_inliers must be >= 0";
   if (c.cg_variant == 2 && c.cg_rtol > 0.0) return "the pipelined CG variant runs a fixed iteration count (cg_rtol = 0)";
@@ -315,7 +317,8 @@ uint32_t solve_epoch_bound(const kf_config& g) {
 bool solve_pipelined(const kf_config& g) { return g.cg_variant == 2 || (g.cg_variant == 0 && g.cg_rtol == 0.0); }
 
 int solve_kind(const kf_config& g) {
-  const bool var = g.variant != KF_VARIANT_FULL || g.lambda_trans > 0.0 || g.lambda_inliers > 0;
+  const bool var = g.variant != KF_VARIANT_FULL || g.robust != KF_ROBUST_HUBER || g.lambda_trans > 0.0 ||
+                   g.lambda_inliers > 0;
   return (solve_pipelined(g) ? 1 : 0) | (var ? 2 : 0);
 }
 
@@ -342,6 +345,7 @@ void solve_args(kf_ctx* c, SolveArgs* a) {
   a->n_cg = g.n_cg;
   a->cg_max = g.cg_max;
   a->variant = g.variant;
+  a->robust = g.robust;
   a->lambda_inliers = g.lambda_inliers;
   a->buf = c->cur;
   a->lambda_trans = g.lambda_trans;

@@ -187,6 +187,7 @@ struct SolveArgs {
   int packed;                // 1: one-word partials (48-bit values, 16-bit epochs)
   int n_gn, n_cg, cg_max;
   int variant;               // kf_variant
+  int robust;                // kf_robust
   int lambda_inliers;        // keyframe rule (0: off)
   int buf;                   // filter-state buffer read (the counters its stereo update wrote)
   double lambda_trans;       // keyframe rule (0: off)

@@ -102,17 +102,23 @@ __device__ inline double wave_sum(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// IRLS weight of a whitened residual: Huber min(1, c / |r|), or Tukey's
+// biweight (1 - (r/c)^2)^2 inside c and 0 beyond.
 template <typename T>
-__device__ inline T huber_w(T r, T delta) {
+__device__ inline T huber_w(T r, T delta, bool tukey = false) {
+  if (tukey) {
+    const T t = r / delta, t2 = t * t;
+    return t2 <= (T)1 ? ((T)1 - t2) * ((T)1 - t2) : (T)0;
+  }
   const T a = fabs(r);
   return a <= delta ? (T)1 : delta / a;
 }
 
 // IRLS weight of the gradient edge between x_a and its right / lower neighbour x_b.
 template <typename T>
-__device__ inline T edge_weight(T xa, T xb, T g, T isd, T delta) {
+__device__ inline T edge_weight(T xa, T xb, T g, T isd, T delta, bool tukey) {
   const T r = ((xb - xa) - g) * isd;
-  return huber_w(r, delta) * isd * isd;
+  return huber_w(r, delta, tukey) * isd * isd;
 }
 
 template <typename T, int NT>
@@ -448,6 +454,7 @@ __device__ __forceinline__ void solve_member(const SolveArgs& a, const int b, un
   // 0 inside the GN loop) and fits the scale afterwards
   const bool nopair = VAR && a.variant == KF_VARIANT_NO_PAIRWISE;
   const bool postfit = VAR && a.variant == KF_VARIANT_SCALE_POSTFIT;
+  const bool tukey = VAR && a.robust == KF_ROBUST_TUKEY;
   double tau = scal->tau;
   const T x_shift = postfit ? (T)tau : (T)0;
   // keyframe rule (Sec. II): a frame that moved the camera too far from the
@@ -517,36 +524,36 @@ __device__ __forceinline__ void solve_member(const SolveArgs& a, const int b, un
       const int i = KF_GI(j), l = KF_LI(j);
       const T xi = xr[j];
       const T mu = mu_g[i], isn = isn_g[i];
-      const T wn = postfit ? (T)0 : huber_w((xi - mu) * isn, delta) * isn * isn;
+      const T wn = postfit ? (T)0 : huber_w((xi - mu) * isn, delta, tukey) * isn * isn;
       T zs;
       const T isr = semi(i, zs);
       T ws = (T)0;
-      if (isr > (T)0) ws = huber_w((xi - (T)tau - zs) * isr, delta) * isr * isr;
+      if (isr > (T)0) ws = huber_w((xi - (T)tau - zs) * isr, delta, tukey) * isr * isr;
       T bb = wn * mu + ws * ((T)tau + zs);
       T cr = 0, cl = 0, cd = 0, cu = 0;
       if (nopair) {
         // per-pixel weighted mean of the network and semi-dense log-depths
-        xr[j] = bb / (wn + ws);
+        if (wn + ws > (T)0) xr[j] = bb / (wn + ws);
         continue;
       }
       if (u < W - 1) {
         const T g = gx_g[i];
-        cr = edge_weight(xi, xs[l + 1], g, isgx_g[i], delta);
+        cr = edge_weight(xi, xs[l + 1], g, isgx_g[i], delta, tukey);
         bb -= cr * g;
       }
       if (u > 0) {
         const T g = gx_g[i - 1];
-        cl = edge_weight(xs[l - 1], xi, g, isgx_g[i - 1], delta);
+        cl = edge_weight(xs[l - 1], xi, g, isgx_g[i - 1], delta, tukey);
         bb += cl * g;
       }
       if (v < H - 1) {
         const T g = gy_g[i];
-        cd = edge_weight(xi, xs[l + rw], g, isgy_g[i], delta);
+        cd = edge_weight(xi, xs[l + rw], g, isgy_g[i], delta, tukey);
         bb -= cd * g;
       }
       if (v > 0) {
         const T g = gy_g[i - W];
-        cu = edge_weight(xs[l - rw], xi, g, isgy_g[i - W], delta);
+        cu = edge_weight(xs[l - rw], xi, g, isgy_g[i - W], delta, tukey);
         bb += cu * g;
       }
       const T d = wn + ws + cr + cl + cd + cu;
@@ -738,7 +745,7 @@ __device__ __forceinline__ void solve_member(const SolveArgs& a, const int b, un
       T zs;
       const T isr = semi(KF_GI(j), zs);
       if (isr > (T)0) {
-        const T w = huber_w((xr[j] - (T)tau - zs) * isr, delta) * isr * isr;
+        const T w = huber_w((xr[j] - (T)tau - zs) * isr, delta, tukey) * isr * isr;
         num += (double)w * (double)(xr[j] - zs);
         den += (double)w;
         cnt += 1.0;

@@ -54,7 +54,7 @@ class KfConfig(ctypes.Structure):
         ("precision", c_int32),
         ("solver_tiles_x", c_int32), ("solver_tiles_y", c_int32),
         ("solver_threads", c_int32), ("solver_cooperative", c_int32), ("pipeline_frames", c_int32),
-        ("variant", c_int32), ("lambda_trans", c_double), ("lambda_inliers", c_int32),
+        ("variant", c_int32), ("robust", c_int32), ("lambda_trans", c_double), ("lambda_inliers", c_int32),
         ("solver_timeout_ms", c_double),
         ("stream", c_void_p), ("workspace", c_void_p), ("workspace_bytes", c_size_t),
     ]
@@ -335,7 +335,7 @@ class Keyframe:
                  huber_delta: float = 1.345, d_near: float = 0.4, d_far: float = 10.0, grad_gate: float = 6.0,
                  sigma_photo: float = 1.0, r_floor: float = 1e-6, K=None, tiles=(0, 0), solver_threads: int = 0,
                  cooperative: bool = False, cg_variant: str = "auto", solver_timeout_ms: float = 0.0,
-                 pipeline_frames: bool = False, variant: str = "full", lambda_trans: float = 0.0,
+                 pipeline_frames: bool = False, variant: str = "full", robust: str = "huber", lambda_trans: float = 0.0,
                  lambda_inliers: int = 0, stream=None):
         torch = _torch()
         if not torch.cuda.is_available():
@@ -356,6 +356,7 @@ class Keyframe:
         cfg.solver_timeout_ms = float(solver_timeout_ms)
         cfg.pipeline_frames = int(bool(pipeline_frames))
         cfg.variant = VARIANTS[variant]
+        cfg.robust = {"huber": 0, "tukey": 1}[robust]
         cfg.lambda_trans, cfg.lambda_inliers = float(lambda_trans), int(lambda_inliers)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         cfg.stream = c_void_p(self.stream.cuda_stream)

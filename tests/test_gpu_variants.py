@@ -104,3 +104,36 @@ def test_variant_end_to_end_f64(c0, variant):
     err = np.abs(np.log(d.cpu().numpy()) - np.log(d_o))
     gu.say(f"[variant-e2e-{variant}] max|dlogd| {err.max():.3e} scale {s:.12f} vs {s_o:.12f}")
     assert err.max() <= 1e-9 and abs(np.log(s / s_o)) <= 1e-9
+
+
+# ------------------------------------------------------------------ Tukey's biweight (Sec. V)
+
+@pytest.mark.parametrize("precision,kw,tol", [("f64", dict(cg_rtol=1e-12, cg_max=4000), 1e-10),
+                                              ("f64", dict(n_cg=20, cg_variant="pipelined"), 1e-10),
+                                              ("f32", dict(n_cg=20), 2e-4)])
+def test_tukey_solver_parity(c0, precision, kw, tol):
+    """Tukey's biweight (c = 4.685) in place of Huber, against the oracle's
+    iteration-matched solve from the same filter state."""
+    gu.say(f"[tukey] config 0 case 0 {precision} {kw}")
+    rho, var = _oracle_state(c0)
+    dt = gu.np_map_dtype(precision)
+    rho_in, var_in = rho.astype(dt), var.astype(dt)
+    kf = _kf(c0, precision, "full", n_gn=10, robust="tukey", huber_delta=4.685, **kw)
+    mdt = gu.map_dtype(precision)
+    kf.import_state(rho=gu.dev(rho_in, mdt), var=gu.dev(var_in, mdt))
+    kf.solve()
+    st = gu.np_state(kf)
+    prm = SolverParams(n_gn=10, n_cg=kw.get("n_cg", 20), cg_rtol=kw.get("cg_rtol", 0.0), cg_max=kw.get("cg_max", 4000),
+                       linear_solver="pcg", robust="tukey", huber_delta=4.685)
+    prior = gu.rounded_priors(c0, precision)
+    semi = gu.oracle_semi(rho_in.astype(np.float64), var_in.astype(np.float64))
+    x_o, tau_o, _ = fusion.gauss_newton(prior.mu, 0.0, prior, semi, prm)
+    err = np.abs(st["x"] - x_o)
+    # Tukey changes the answer: compare with Huber to show the option is live
+    x_h, _, _ = fusion.gauss_newton(prior.mu, 0.0, prior, semi, SolverParams(n_gn=10, cg_rtol=1e-12, linear_solver="pcg"))
+    gu.say(f"[tukey-{precision}] max|dx| {err.max():.3e} rms {np.sqrt(np.mean(err ** 2)):.3e} dtau "
+           f"{abs(st['tau'] - tau_o):.3e}; Tukey vs Huber max|dx| {np.abs(x_o - x_h).max():.3e}")
+    assert err.max() <= tol and abs(st["tau"] - tau_o) <= tol
+    if precision != "f64":
+        assert np.sqrt(np.mean(err ** 2)) <= 2e-5
+    assert np.abs(x_o - x_h).max() > 1e-4

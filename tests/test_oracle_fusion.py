@@ -370,3 +370,67 @@ def test_scale_postfit_solve_is_stationary_for_semi_and_gradient_terms():
     g0, _ = fusion.cost_gradient(prior.mu, 0.0, _no_net(prior), semi, DELTA)
     g, _ = fusion.cost_gradient(y, 0.0, _no_net(prior), semi, DELTA)
     assert np.sqrt(np.sum(g * g)) <= 1e-9 * np.sqrt(np.sum(g0 * g0))
+
+
+# ------------------------------------------------------------------ Tukey's biweight (Sec. V)
+
+def test_tukey_weight_is_derivative_ratio_and_cost_matches_finite_differences():
+    """R26: T'(r) / (2 r) is the IRLS weight; T' agrees with central differences
+    of T; T ~ r^2 for small r and is flat (c^2/3) beyond c."""
+    c = 4.685
+    r = np.linspace(-9.0, 9.0, 1001)
+    r = r[np.abs(np.abs(r) - c) > 1e-3]
+    h = 1e-6
+    fd = (fusion.tukey(r + h, c) - fusion.tukey(r - h, c)) / (2 * h)
+    assert np.allclose(fusion.tukey_derivative(r, c), fd, atol=1e-6)
+    nz = np.abs(r) > 1e-3
+    assert np.allclose(fusion.tukey_weight(r[nz], c), fusion.tukey_derivative(r[nz], c) / (2 * r[nz]), atol=1e-12)
+    assert np.allclose(fusion.tukey(np.array([1e-4]), c), 1e-8, rtol=1e-6)
+    assert np.all(fusion.tukey(np.array([c, 2 * c, 50.0]), c) == c * c / 3.0)
+    assert np.all(fusion.tukey_weight(np.array([c * 1.0001, 10 * c]), c) == 0.0)
+
+
+def test_tukey_with_a_huge_threshold_is_least_squares():
+    """c -> infinity: every weight -> 1, so Tukey's scheme equals plain least squares."""
+    prior, semi, _ = _problem(8, 9, seed=31)
+    a = fusion.gauss_newton(prior.mu, 0.0, prior, semi, SolverParams(n_gn=4, huber_delta=1e7, robust="tukey",
+                                                                      linear_solver="direct"))
+    b = fusion.gauss_newton(prior.mu, 0.0, prior, semi, SolverParams(n_gn=4, huber_delta=np.inf,
+                                                                      linear_solver="direct"))
+    assert np.max(np.abs(a[0] - b[0])) <= 1e-9 and abs(a[1] - b[1]) <= 1e-9
+
+
+def test_tukey_rejects_a_gross_outlier_exactly():
+    """A semi-dense measurement whose whitened residual stays beyond c at every
+    iterate gets weight 0: the result equals the problem without it (Huber would
+    still pull on it)."""
+    prior, semi, _ = _problem(8, 10, seed=32, outliers=0.0)
+    S = np.argwhere(semi.valid)
+    v, u = S[len(S) // 2]
+    z2 = semi.z.copy()
+    z2[v, u] += 3.0                                       # whitened residual ~ 3 / 0.1 = 30 >> c
+    bad = SemiMeasurements(z2, semi.R, semi.valid)
+    keep = semi.valid.copy()
+    keep[v, u] = False
+    drop = SemiMeasurements(np.where(keep, semi.z, 0.0), np.where(keep, semi.R, np.inf), keep)
+    prm = SolverParams(n_gn=6, huber_delta=4.685, robust="tukey", linear_solver="direct")
+    a = fusion.gauss_newton(prior.mu, 0.0, prior, bad, prm)
+    b = fusion.gauss_newton(prior.mu, 0.0, prior, drop, prm)
+    assert np.max(np.abs(a[0] - b[0])) <= 1e-12 and abs(a[1] - b[1]) <= 1e-12
+    hub = fusion.gauss_newton(prior.mu, 0.0, prior, bad, SolverParams(n_gn=6, huber_delta=4.685,
+                                                                       linear_solver="direct"))
+    hub0 = fusion.gauss_newton(prior.mu, 0.0, prior, drop, SolverParams(n_gn=6, huber_delta=4.685,
+                                                                         linear_solver="direct"))
+    assert np.max(np.abs(hub[0] - hub0[0])) > 1e-6
+
+
+def test_tukey_irls_does_not_increase_the_cost():
+    """IRLS with exact solves is a majorise-minimise scheme for Tukey's cost: each
+    weighted least-squares step and each closed-form scale step lowers (or keeps)
+    the Tukey cost."""
+    prior, semi, _ = _problem(9, 11, seed=33, outliers=0.15)
+    prm = SolverParams(n_gn=12, huber_delta=4.685, robust="tukey", linear_solver="direct")
+    c0 = fusion.cost(prior.mu, 0.0, prior, semi, 4.685, "tukey")
+    _, _, info = fusion.gauss_newton(prior.mu, 0.0, prior, semi, prm)
+    costs = [c0] + info.costs
+    assert all(b <= a * (1 + 1e-12) for a, b in zip(costs, costs[1:]))
