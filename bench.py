@@ -1,6 +1,7 @@
 """Throughput / latency benchmark of the keyframe depth update on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py --sync-sweep      (team-synchronisation latency vs team size)
 
 Workload (default): one 640 x 480 keyframe fused with a 30-frame sequence in the
 precision form (bf16 keyframe image and patch buffers, fp32 maps and arithmetic,
@@ -592,26 +593,79 @@ def run_headline(a, torch):
     return out
 
 
+def probe_us_per_sync(kf, torch, rounds, nvalues=2, repeats=3):
+    """Microseconds per round of the synchronisation probe (kf_probe_sync), one
+    warm-up launch, then the fastest of `repeats` launches timed with HIP events
+    on the context's stream."""
+    kf.probe_sync(rounds, nvalues)
+    best = None
+    for _ in range(repeats):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(kf.stream)
+        kf.probe_sync(rounds, nvalues)
+        e1.record(kf.stream)
+        e1.synchronize()
+        us = e0.elapsed_time(e1) * 1000.0 / rounds
+        best = us if best is None else min(best, us)
+    return best
+
+
 def sync_floor(kf, torch, syncs, solve_ms, rounds=2000):
     """Team-synchronisation floor of the solve: the probe launch (same team,
     tiling and exchange as the solve, no arithmetic) timed with HIP events on
     the context's stream; floor = synchronisations per solve x time per probe
     round."""
-    kf.probe_sync(rounds, 2)
-    best = None
-    for _ in range(3):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(kf.stream)
-        kf.probe_sync(rounds, 2)
-        e1.record(kf.stream)
-        e1.synchronize()
-        us = e0.elapsed_time(e1) * 1000.0 / rounds
-        best = us if best is None else min(best, us)
+    best = probe_us_per_sync(kf, torch, rounds)
     floor_ms = syncs * best / 1000.0
     return {"syncs_per_launch": syncs, "probe_us_per_sync": round(best, 4), "floor_ms": round(floor_ms, 4),
             "frac": round(floor_ms / solve_ms, 4),
             "probe": f"kf_probe_sync: {rounds} exchanges of 2 partials + the tile boundary, same team and tiling "
                      "as the solve, no arithmetic; fastest of 3 launches"}
+
+
+# team shapes (tiles_x, tiles_y) of the synchronisation sweep, up to the largest
+# team of one keyframe (256 workgroups); every tile is 40 x 30 pixels, the
+# 640 x 480 solve's tile at 16 x 16
+SYNC_SWEEP_TEAMS = ((1, 1), (2, 1), (2, 2), (4, 4), (8, 4), (8, 8), (10, 10), (12, 12), (16, 12), (16, 16))
+SYNC_SWEEP_TILE = (40, 30)
+
+
+def run_sync_sweep(torch, rounds=2000, threads=512):
+    """Exchange latency against team size: for each team shape a keyframe of
+    (40 tiles_x) x (30 tiles_y) pixels at that tiling, and the probe's time per
+    synchronisation with 1, 2 and 3 published values (a CG iteration of the
+    pipelined solve publishes 2, the textbook one 1 per synchronisation), in the
+    float forms (one 64-bit word per partial) and FP64 (two words)."""
+    from paper_2207_12244_amd.kf import Keyframe, KfError
+    rows = []
+    for precision in ("f32", "f64"):
+        for tx, ty in SYNC_SWEEP_TEAMS:
+            W, H = SYNC_SWEEP_TILE[0] * tx, SYNC_SWEEP_TILE[1] * ty
+            row = {"precision": precision, "tiles": [tx, ty], "workgroups": tx * ty, "size": [W, H],
+                   "threads": threads}
+            try:
+                kf = Keyframe(W, H, precision=precision, pattern="sq5x5", n_samples=128, tiles=(tx, ty),
+                              solver_threads=threads)
+            except KfError as e:
+                rows.append({**row, "skipped": str(e)})
+                continue
+            dt = kf.dtype
+            zero = torch.zeros((H, W), dtype=dt, device="cuda")
+            one = torch.ones((H, W), dtype=dt, device="cuda")
+            img = torch.zeros((H, W), dtype=torch.uint8, device="cuda")
+            kf.set_prior(img, zero, one, zero, one, zero, one, np.eye(4))
+            try:
+                row["us_per_sync"] = {str(nv): round(probe_us_per_sync(kf, torch, rounds, nv), 4) for nv in (1, 2, 3)}
+            except KfError as e:
+                row["skipped"] = str(e)
+            kf.close()
+            rows.append(row)
+            print(f"# sync sweep {precision} {tx}x{ty} ({tx * ty} workgroups, {W}x{H}): "
+                  f"{row.get('us_per_sync', row.get('skipped'))}", file=sys.stderr, flush=True)
+    return {"sync_sweep": rows, "rounds": rounds,
+            "probe": "kf_probe_sync: per round, every workgroup publishes nvalues partials and its tile boundary "
+                     "and polls the team's partials and its neighbours' boundaries, no arithmetic; us per round = "
+                     "the fastest of 3 launches timed with HIP events, after one warm-up launch"}
 
 
 def main(argv=None):
@@ -630,6 +684,8 @@ def main(argv=None):
     ap.add_argument("--serving-tiles", default="auto", choices=["tuned", "auto"],
                     help="serving tile shapes: latency-optimal per size (auto) or the batch autotuner's")
     ap.add_argument("--batched-steps", type=int, default=10)
+    ap.add_argument("--sync-sweep", action="store_true",
+                    help="only measure the team-synchronisation latency against team size (kf_probe_sync)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 256 MiB device-to-device copy (HBM counter calibration)")
     a = ap.parse_args(argv)
@@ -638,6 +694,14 @@ def main(argv=None):
               "independent keyframes shard across GPUs without communication, see the design notes.",
               file=sys.stderr)
         return 2
+
+    if a.sync_sweep:
+        import torch
+        if not torch.cuda.is_available():
+            print("bench.py needs a GPU", file=sys.stderr)
+            return 2
+        print(json.dumps(run_sync_sweep(torch)), flush=True)
+        return 0
 
     # the batched and serving workloads are generated in process pools before the GPU is touched
     batched_in = batched_cases(BATCHED["keyframes"]) if a.form in ("all", "batched") else None

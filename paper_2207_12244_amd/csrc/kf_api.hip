@@ -159,7 +159,7 @@ bool layout_for(const kf_config& c, const Tiling& t, Layout* L) {
   L->i1s = off; off += align256((size_t)(c.height + 1) * stage_stride(c.width));
   L->scal = off; off += 256;
   L->parts = off; off += align256((size_t)2 * NV_MAX * PART_REPLICAS * t.blocks * 2 * 8);
-  L->halo = off; off += align256((size_t)2 * t.blocks * (2 * t.tile_w + 2 * t.tile_h) * 2 * 8);
+  L->halo = off; off += align256((size_t)2 * t.blocks * 2 * (2 * t.tile_w + 2 * t.tile_h) * 2 * 8);
   L->total = off;
   return true;
 }
@@ -339,6 +339,9 @@ void solve_args(kf_ctx* c, SolveArgs* a) {
   a->parts = ws_ptr<uint64_t>(c, c->lay.parts);
   a->halo = ws_ptr<uint64_t>(c, c->lay.halo);
   a->perim = 2 * c->tiling.tile_w + 2 * c->tiling.tile_h;
+  // the second-ring cells (perimeter + 4 corners) fit one slot per thread
+  a->ghost_z = (solve_pipelined(g) && g.cg_rtol == 0.0 && c->tiling.tile_w >= 2 && c->tiling.tile_h >= 2 &&
+                a->perim + 4 <= c->tiling.threads) ? 1 : 0;
   a->epoch_span = bound;
   a->packed = (g.precision != KF_F64 && bound < 30000) ? 1 : 0;
   a->n_gn = g.n_gn;

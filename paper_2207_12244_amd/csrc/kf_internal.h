@@ -181,8 +181,10 @@ struct SolveArgs {
   void* x;
   DevScalars* scal;
   uint64_t* parts;           // [2][NV_MAX][PART_REPLICAS][blocks][2] exchange words
-  uint64_t* halo;            // [2][blocks][perim][2]
+  uint64_t* halo;            // [2][blocks][2 perim][2]: first, then second row / column per side
   int perim;                 // 2 tile_w + 2 tile_h
+  int ghost_z;               // 1: fixed-count pipelined CG on tiles >= 2 x 2 without the
+                             // initial-residual synchronisation (x shipped two pixels deep)
   uint32_t epoch_span;       // epochs one launch may use (the base lives in DevScalars::epoch)
   int packed;                // 1: one-word partials (48-bit values, 16-bit epochs)
   int n_gn, n_cg, cg_max;

@@ -20,7 +20,10 @@
 // next stencil operand) or 2 (textbook variant: p.q; then r.z with the z
 // boundary from which every member rebuilds its ghost copy of p, the last r.z
 // skipped in fixed-count mode), and 1 for the scale step (which also ships the
-// x boundary).
+// x boundary). The fixed-count pipelined variant skips the initial-residual
+// synchronisation: its scale step ships x two pixels deep (plus the diagonal
+// neighbours' corner pixels), from which each member assembles the ghost
+// values of the first stencil operand itself.
 #include "kf_internal.h"
 
 namespace kf {
@@ -28,6 +31,7 @@ namespace kf {
 namespace {
 
 constexpr int GMAX = 2;      // ghost slots per thread: ghost ring <= GMAX * threads cells
+constexpr int G2MAX = 1;     // second-ring slots per thread: second ring + 4 corners <= threads cells
 
 __device__ inline void st_word(KF_GLOBAL uint64_t* p, uint64_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -85,21 +89,18 @@ __device__ inline double dpp_d(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Sum over the 64 lanes, returned in every lane, in a fixed order: an
-// inclusive scan inside each 16-lane row (shifts 1, 2, 4, 8), then the row
-// totals are carried with the row broadcasts 15 and 31; lane 63 ends with the
-// total, which is read back as a scalar.
-__device__ inline double wave_sum(double v) {
+// Sum over the 64 lanes in a fixed order: an inclusive scan inside each
+// 16-lane row (shifts 1, 2, 4, 8), then the row totals are carried with the
+// row broadcasts 15 and 31; lane 63 ends with the total (other lanes hold
+// partial sums).
+__device__ inline double wave_total_lane63(double v) {
   v += dpp_d<0x111, 0xf, true>(v);   // row_shr:1
   v += dpp_d<0x112, 0xf, true>(v);   // row_shr:2
   v += dpp_d<0x114, 0xf, true>(v);   // row_shr:4
   v += dpp_d<0x118, 0xf, true>(v);   // row_shr:8
   v += dpp_d<0x142, 0xa, false>(v);  // row_bcast:15 into rows 1 and 3
   v += dpp_d<0x143, 0xc, false>(v);  // row_bcast:31 into rows 2 and 3
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), 63);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+  return v;
 }
 
 // IRLS weight of a whitened residual: Huber min(1, c / |r|), or Tukey's
@@ -128,6 +129,7 @@ struct Team {
   static constexpr int CPV = MAX_TEAM / 64;                            // 64-slot chunks per value, at most
   int B, b, tw, th, rw, perim, tile_w, tile_h;
   int nb_up, nb_dn, nb_lf, nb_rt;
+  int tiles_x;
   KF_GLOBAL uint64_t* parts;
   KF_GLOBAL uint64_t* halo;
   KF_GLOBAL int32_t* err;
@@ -140,6 +142,12 @@ struct Team {
   int g_src[GMAX];  // neighbour workgroup or -1
   int g_off[GMAX];  // offset in its boundary list
   int g_li[GMAX];   // ring index
+  // second-ring slots of this thread (two-deep x boundary, see publish_ring2):
+  // neighbour (or diagonal neighbour) workgroup or -1, offset in its boundary
+  // lists, destination index relative to the x ring
+  int g2_src[G2MAX];
+  int g2_off[G2MAX];
+  int g2_li[G2MAX];
 
   // Replica r of member j's partial v: every member writes all replicas and
   // reads replica (own index mod PART_REPLICAS), so the team's polling loads
@@ -147,8 +155,10 @@ struct Team {
   __device__ KF_GLOBAL uint64_t* part_slot(uint32_t e, int v, int j, int r) const {
     return parts + ((size_t)(((e & 1u) * NV_MAX + v) * PART_REPLICAS + r) * B + j) * 2;
   }
+  // Boundary lists of member blk: [0, perim) its first row / column per side,
+  // [perim, 2 perim) its second row / column per side (publish_ring2).
   __device__ KF_GLOBAL uint64_t* halo_slot(uint32_t e, int blk, int off) const {
-    return halo + ((size_t)((e & 1u) * B + blk) * perim + off) * 2;
+    return halo + ((size_t)((e & 1u) * B + blk) * (2 * perim) + off) * 2;
   }
 
   // Publishes the boundary value of own pixel (lx, ly) for the neighbours that read it.
@@ -180,6 +190,29 @@ struct Team {
     }
   }
 
+  // Publishes the second row / column of each side (row 1 for the member
+  // above, row th - 2 below, column 1 to the left, column tw - 2 to the right)
+  // from the ring of own values: with the first ones and the diagonal
+  // neighbours' corner pixels, a neighbour holds the tile's x two pixels deep.
+  __device__ void publish_ring2(uint32_t e, const T* ring) const {
+    int s = threadIdx.x;
+    refresh(s);
+    for (; s < perim; s += NT) {
+      int lx, ly, nb;
+      if (s < tile_w) {
+        lx = s; ly = 1; nb = nb_up;
+      } else if (s < 2 * tile_w) {
+        lx = s - tile_w; ly = th - 2; nb = nb_dn;
+      } else if (s < 2 * tile_w + tile_h) {
+        lx = 1; ly = s - 2 * tile_w; nb = nb_lf;
+      } else {
+        lx = tw - 2; ly = s - 2 * tile_w - tile_h; nb = nb_rt;
+      }
+      if (nb >= 0 && lx >= 0 && ly >= 0 && lx < tw && ly < th)
+        Wire<T>::put(halo_slot(e, b, perim + s), ring[(ly + 1) * rw + lx + 1], e);
+    }
+  }
+
   // Team-wide sums of nv per-thread partials and, if `ghosts`, the neighbours'
   // published boundary values for this thread's ghost slots (stored into
   // `ring` too when given). With `ring_pub` the own boundary is published from
@@ -191,13 +224,15 @@ struct Team {
   // team aborts.
   __device__ bool sync(uint32_t e, int nv, const double* vals, double* tot, T* gval, bool ghosts, T* ring = nullptr,
                        bool ring_pub = false) {
-    return sync(e, nv, vals, tot, gval, ghosts, ring, ring_pub, [] {});
+    return this->template sync<false>(e, nv, vals, tot, gval, ghosts, ring, ring_pub, [] {});
   }
 
   // As above; `pre()` runs in every thread after the workgroup has published
   // its partials and before it polls: work that needs no neighbour data (and
-  // may read LDS written before the synchronisation) overlaps the wait.
-  template <typename F>
+  // may read LDS written before the synchronisation) overlaps the wait. With
+  // R2 the second-ring slots are polled too, into `ring` at g2_li (the caller
+  // publishes its own second rows in `pre`).
+  template <bool R2, typename F>
   __device__ bool sync(uint32_t e, int nv, const double* vals, double* tot, T* gval, bool ghosts, T* ring, bool ring_pub,
                        F&& pre) {
     int tid = threadIdx.x;
@@ -209,9 +244,15 @@ struct Team {
       refresh(g_off[m]);
       refresh(g_li[m]);
     }
-    for (int v = 0; v < nv; ++v) {
-      const double s = wave_sum(vals[v]);
-      if (lane == 0) s_wred[wave * NV_MAX + v] = s;
+    // the nv scans are independent, so their DPP chains interleave; lane 63
+    // holds each total and stores it (no read-back through a scalar)
+    double wsum[NV_MAX];
+#pragma unroll
+    for (int v = 0; v < NV_MAX; ++v) wsum[v] = v < nv ? wave_total_lane63(vals[v]) : 0.0;
+    if (lane == 63) {
+#pragma unroll
+      for (int v = 0; v < NV_MAX; ++v)
+        if (v < nv) s_wred[wave * NV_MAX + v] = wsum[v];
     }
     __syncthreads();
     if (tid < nv * PART_REPLICAS) {
@@ -228,8 +269,8 @@ struct Team {
     // polls slots of one value only and can reduce them itself
     const int Bp = (B + 63) & ~63;
     const int nslots = nv * Bp;
-    bool p_ready[PSLOTS], g_ready[GMAX];
-    uint64_t pw0[PSLOTS], pw1[PSLOTS], gw0[GMAX], gw1[GMAX];
+    bool p_ready[PSLOTS], g_ready[GMAX], g2_ready[G2MAX];
+    uint64_t pw0[PSLOTS], pw1[PSLOTS], gw0[GMAX], gw1[GMAX], g2w0[G2MAX], g2w1[G2MAX];
     double pval[PSLOTS];   // decoded partials; padding slots keep 0
     const KF_GLOBAL uint64_t* p_addr[PSLOTS];
     const int cpv = Bp >> 6;   // chunks per value
@@ -243,6 +284,16 @@ struct Team {
     }
 #pragma unroll
     for (int m = 0; m < GMAX; ++m) g_ready[m] = !(ghosts && g_src[m] >= 0);
+#pragma unroll
+    for (int m = 0; m < G2MAX; ++m) {
+      g2_ready[m] = !(R2 && g2_src[m] >= 0);
+      g2w0[m] = g2w1[m] = 0;
+      if (R2) {
+        refresh(g2_src[m]);
+        refresh(g2_off[m]);
+        refresh(g2_li[m]);
+      }
+    }
     unsigned spins = 0;
     uint64_t t0 = 0;
     bool ok = true;
@@ -262,6 +313,14 @@ struct Team {
           const KF_GLOBAL uint64_t* w = halo_slot(e, g_src[m], g_off[m]);
           gw0[m] = ld_word(w);
           if (Wire<T>::N == 2) gw1[m] = ld_word(w + 1);
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < G2MAX; ++m) {
+        if (R2 && !g2_ready[m]) {
+          const KF_GLOBAL uint64_t* w = halo_slot(e, g2_src[m], g2_off[m]);
+          g2w0[m] = ld_word(w);
+          if (Wire<T>::N == 2) g2w1[m] = ld_word(w + 1);
         }
       }
 #pragma unroll
@@ -288,6 +347,17 @@ struct Team {
           }
         }
       }
+#pragma unroll
+      for (int m = 0; m < G2MAX; ++m) {
+        if (R2 && !g2_ready[m]) {
+          if ((uint32_t)(g2w0[m] >> 32) == e && (Wire<T>::N == 1 || (uint32_t)(g2w1[m] >> 32) == e)) {
+            g2_ready[m] = true;
+            ring[g2_li[m]] = Wire<T>::make((uint32_t)g2w0[m], (uint32_t)g2w1[m]);
+          } else {
+            all = false;
+          }
+        }
+      }
       if (all) break;
       if ((++spins & 63u) == 0u) {
         const uint64_t now = wall_clock64();
@@ -309,9 +379,9 @@ struct Team {
     for (int q = 0; q < PSLOTS; ++q) {
       const int chunk = (q * NT + tid) >> 6;
       if (chunk * 64 < nslots) {
-        const double cs = wave_sum(pval[q]);
+        const double cs = wave_total_lane63(pval[q]);
         const int v = chunk / cpv;
-        if (lane == 0) s_pol[v * CPV + chunk - v * cpv] = cs;
+        if (lane == 63) s_pol[v * CPV + chunk - v * cpv] = cs;
       }
     }
     __syncthreads();
@@ -334,13 +404,37 @@ struct Team {
 
 // LDS of one member: [NW][NV_MAX] wave partials, [NV_MAX][CPV] team chunk
 // partials, abort flag, then three rings of (tile_h + 2) x (tile_w + 2):
-// x and two stencil operands.
+// x and two stencil operands, then the second ring of x (2 tile_w + 2 tile_h:
+// top, bottom, left, right; its corners sit in the corner cells of the x ring),
+// then 12 x (2 tile_w + 2 tile_h) static row inputs of the ghost cells.
 template <typename T, int NT>
 struct MemberLds {
   T* xs;
   T* ps;
   T* ms0;
+  T* x2;
+  T* gdat;
 };
+
+// Tile coordinates of cell g of the second ring of x: [0, tw) the row above
+// the ghost row, then the row below, the column left of the ghost column, the
+// column right of it, then the four ghost-ring corners (-1, -1), (tw, -1),
+// (-1, th), (tw, th).
+__device__ inline void ring2_cell(int g, int tw, int th, int& cx, int& cy) {
+  if (g < tw) {
+    cx = g; cy = -2;
+  } else if (g < 2 * tw) {
+    cx = g - tw; cy = th + 1;
+  } else if (g < 2 * tw + th) {
+    cx = -2; cy = g - 2 * tw;
+  } else if (g < 2 * tw + 2 * th) {
+    cx = tw + 1; cy = g - 2 * tw - th;
+  } else {
+    const int k = g - 2 * tw - 2 * th;
+    cx = (k & 1) ? tw : -1;
+    cy = (k & 2) ? th : -1;
+  }
+}
 
 // Sets up member b (tile b) of the team of `a`: tile geometry, neighbours,
 // exchange words, LDS carve-up (cleared) and this thread's ghost slots (top
@@ -365,6 +459,7 @@ __device__ __forceinline__ void team_init(Team<T, NT>& tm, MemberLds<T, NT>& lds
   tm.nb_dn = by < a.tiles_y - 1 ? b + a.tiles_x : -1;
   tm.nb_lf = bx > 0 ? b - 1 : -1;
   tm.nb_rt = bx < a.tiles_x - 1 ? b + 1 : -1;
+  tm.tiles_x = a.tiles_x;
   tm.parts = gp(a.parts);
   tm.halo = gp(a.halo);
   tm.err = &gp(a.scal)->err;
@@ -378,7 +473,9 @@ __device__ __forceinline__ void team_init(Team<T, NT>& tm, MemberLds<T, NT>& lds
   lds.xs = reinterpret_cast<T*>(dsm + NW * NV_MAX + NV_MAX * Team<T, NT>::CPV + 2);
   lds.ps = lds.xs + ring_max;
   lds.ms0 = lds.ps + ring_max;
-  for (int i = tid; i < 3 * ring_max; i += NT) lds.xs[i] = (T)0;
+  lds.x2 = lds.ms0 + ring_max;
+  lds.gdat = lds.x2 + a.perim;
+  for (int i = tid; i < 3 * ring_max + a.perim; i += NT) lds.xs[i] = (T)0;
   if (tid < NV_MAX * Team<T, NT>::CPV) tm.s_pol[tid] = 0.0;
   if (tid == 0) *tm.s_abort = 0;
   const int tw = tm.tw, th = tm.th, rw = tm.rw;
@@ -403,6 +500,38 @@ __device__ __forceinline__ void team_init(Team<T, NT>& tm, MemberLds<T, NT>& lds
         tm.g_src[m] = tm.nb_rt; tm.g_off[m] = 2 * a.tile_w + ly; tm.g_li[m] = (ly + 1) * rw + tw + 1;
       }
     }
+  }
+  // second-ring slots: the neighbours' second rows / columns (published by
+  // publish_ring2) where that pixel is inside the image, and the diagonal
+  // neighbours' corner pixels from their first-row lists
+  const int x2b = 3 * ring_max;   // index of the second ring relative to xs
+  const int ncell = 2 * tw + 2 * th;
+#pragma unroll
+  for (int m = 0; m < G2MAX; ++m) {
+    const int g = tid + m * NT;
+    int src = -1, off = 0, li = 0;
+    if (a.ghost_z && g < ncell + 4) {
+      if (g < tw) {
+        src = tm.nb_up; off = a.perim + a.tile_w + g; li = x2b + g;
+      } else if (g < 2 * tw) {
+        src = (tm.nb_dn >= 0 && oy + th + 1 < H) ? tm.nb_dn : -1; off = a.perim + (g - tw); li = x2b + g;
+      } else if (g < 2 * tw + th) {
+        src = tm.nb_lf; off = a.perim + 2 * a.tile_w + a.tile_h + (g - 2 * tw); li = x2b + g;
+      } else if (g < ncell) {
+        src = (tm.nb_rt >= 0 && ox + tw + 1 < W) ? tm.nb_rt : -1; off = a.perim + 2 * a.tile_w + (g - 2 * tw - th);
+        li = x2b + g;
+      } else {
+        const int k = g - ncell;
+        const bool up = !(k & 2), left = !(k & 1);
+        const int nbv = up ? tm.nb_up : tm.nb_dn, nbh = left ? tm.nb_lf : tm.nb_rt;
+        src = (nbv >= 0 && nbh >= 0) ? b + (up ? -a.tiles_x : a.tiles_x) + (left ? -1 : 1) : -1;
+        off = (up ? a.tile_w : 0) + (left ? a.tile_w - 1 : 0);
+        li = (up ? 0 : (th + 1) * rw) + (left ? 0 : tw + 1);
+      }
+    }
+    tm.g2_src[m] = src;
+    tm.g2_off[m] = off;
+    tm.g2_li[m] = li;
   }
   __syncthreads();
 }
@@ -481,6 +610,15 @@ __device__ __forceinline__ void solve_member(const SolveArgs& a, const int b, un
       xs[li_g] = x_g[(oy + gy_) * W + ox + gx_] - x_shift;
     }
   }
+  // and its second ring (slots only where that pixel is inside the image)
+#pragma unroll
+  for (int m = 0; m < G2MAX; ++m) {
+    if (tm.g2_src[m] >= 0) {
+      int cx, cy;
+      ring2_cell(tid + m * NT, tw, th, cx, cy);
+      xs[tm.g2_li[m]] = x_g[(oy + cy) * W + ox + cx] - x_shift;
+    }
+  }
   if (postfit && !new_kf) tau = 0.0;
   __syncthreads();
 
@@ -511,72 +649,194 @@ __device__ __forceinline__ void solve_member(const SolveArgs& a, const int b, un
     return (T)1 / sqrt(R);
   };
 
+  // The static inputs of one row of the 5-point normal equations at pixel
+  // i = (u, v): network log-depth and its inverse sigma, the semi-dense
+  // measurement, and per gradient edge (right, left, lower, upper) the prior
+  // gradient and its inverse sigma (zeros for an edge that leaves the image).
+  struct RowData {
+    T mu, isn, zs, isr, gR, sR, gL, sL, gD, sD, gU, sU;
+  };
+  auto row_data = [&](int i, int u, int v) -> RowData {
+    RowData r;
+    r.mu = mu_g[i];
+    r.isn = isn_g[i];
+    r.isr = semi(i, r.zs);
+    r.gR = r.sR = r.gL = r.sL = r.gD = r.sD = r.gU = r.sU = (T)0;
+    if (u < W - 1) {
+      r.gR = gx_g[i]; r.sR = isgx_g[i];
+    }
+    if (u > 0) {
+      r.gL = gx_g[i - 1]; r.sL = isgx_g[i - 1];
+    }
+    if (v < H - 1) {
+      r.gD = gy_g[i]; r.sD = isgy_g[i];
+    }
+    if (v > 0) {
+      r.gU = gy_g[i - W]; r.sU = isgy_g[i - W];
+    }
+    return r;
+  };
+
+  // The row (Sec. II-C) at log-depth xi with its right / left / lower / upper
+  // neighbours' values: IRLS weights of the unary terms, couplings of the
+  // gradient edges (none for an edge that leaves the image, none at all
+  // without `edges`), diagonal and right-hand side. Own pixels and ghost
+  // pixels share it, so a ghost row repeats its owner's arithmetic.
+  struct Row {
+    T wn, ws, bb, cr, cl, cd, cu, d;
+  };
+  auto row_at = [&](const RowData& r, int u, int v, T xi, T xR, T xL, T xD, T xU, bool edges) -> Row {
+    Row q;
+    q.wn = postfit ? (T)0 : huber_w((xi - r.mu) * r.isn, delta, tukey) * r.isn * r.isn;
+    q.ws = (T)0;
+    if (r.isr > (T)0) q.ws = huber_w((xi - (T)tau - r.zs) * r.isr, delta, tukey) * r.isr * r.isr;
+    T bb = q.wn * r.mu + q.ws * ((T)tau + r.zs);
+    T cr = 0, cl = 0, cd = 0, cu = 0;
+    if (edges) {
+      if (u < W - 1) {
+        cr = edge_weight(xi, xR, r.gR, r.sR, delta, tukey);
+        bb -= cr * r.gR;
+      }
+      if (u > 0) {
+        cl = edge_weight(xL, xi, r.gL, r.sL, delta, tukey);
+        bb += cl * r.gL;
+      }
+      if (v < H - 1) {
+        cd = edge_weight(xi, xD, r.gD, r.sD, delta, tukey);
+        bb -= cd * r.gD;
+      }
+      if (v > 0) {
+        cu = edge_weight(xU, xi, r.gU, r.sU, delta, tukey);
+        bb += cu * r.gU;
+      }
+    }
+    q.bb = bb;
+    q.cr = cr; q.cl = cl; q.cd = cd; q.cu = cu;
+    q.d = q.wn + q.ws + cr + cl + cd + cu;
+    return q;
+  };
+
+  // Fixed-count pipelined CG with tiles at least 2 x 2: the first stencil
+  // operand's ghost values are assembled locally (x is known two pixels deep
+  // around the tile), which saves the initial-residual synchronisation of
+  // every GN iteration. gz_c0: this thread's first ghost cell; the cells start
+  // at the first wavefront whose threads hold one pixel fewer than PPT.
+  const bool ghost_z = PIPE && !tol_mode && a.ghost_z != 0;
+  T* x2 = lds.x2;
+  T* gdat = lds.gdat;   // [12][perim]: the ghost cells' RowData, filled once per launch
+  const int perim = a.perim;
+  int gz_c0;
+  {
+    const int full = npx - (PPT - 1) * NT;   // threads [0, full) hold PPT pixels
+    int t0 = full <= 0 ? 0 : ((full + 63) / 64) * 64;
+    t0 = t0 < NT ? t0 : 0;
+    gz_c0 = tid - t0;
+    if (gz_c0 < 0) gz_c0 += NT;
+  }
+  // ghost cell c of the first ring: tile coordinates and the neighbour that owns it (-1: none)
+  auto ghost_cell = [&](int c, int& gx, int& gy) -> int {
+    if (c < tw) {
+      gx = c; gy = -1; return tm.nb_up;
+    } else if (c < 2 * tw) {
+      gx = c - tw; gy = th; return tm.nb_dn;
+    } else if (c < 2 * tw + th) {
+      gx = -1; gy = c - 2 * tw; return tm.nb_lf;
+    }
+    gx = tw; gy = c - 2 * tw - th; return tm.nb_rt;
+  };
+  if (ghost_z && !nopair) {
+    // the static part of this thread's ghost rows, read once; the same thread
+    // reads it back in every GN iteration (no barrier needed)
+#pragma unroll
+    for (int m = 0; m < GMAX; ++m) {
+      const int c = gz_c0 + m * NT;
+      if (c >= 2 * tw + 2 * th) continue;
+      int gx, gy;
+      if (ghost_cell(c, gx, gy) < 0) continue;
+      const int u = ox + gx, v = oy + gy;
+      const RowData r = row_data(v * W + u, u, v);
+      const T vals12[12] = {r.mu, r.isn, r.zs, r.isr, r.gR, r.sR, r.gL, r.sL, r.gD, r.sD, r.gU, r.sU};
+#pragma unroll
+      for (int k = 0; k < 12; ++k) gdat[k * perim + c] = vals12[k];
+    }
+  }
+
   for (int gn = 0; gn < (new_kf ? 0 : a.n_gn); ++gn) {
 #pragma unroll
     for (int j = 0; j < PPT; ++j) refresh(lxy[j]);
     // ---- IRLS weights and 5-point normal equations at (x, tau) (Sec. II-C);
     //      r = b - A x, z = r / diag, p = z
     double rz = 0.0, r2 = 0.0, b2 = 0.0;
+    if (ghost_z && !nopair) {
+      // z of the ghost ring assembled here from the two-deep x boundary (the
+      // same row arithmetic as its owner's), instead of a synchronisation that
+      // ships it; cells spread over the threads with the fewest own pixels
+      // (the cell index is redefined here, so the compiler forms the cells'
+      // addresses inside the GN loop instead of keeping them live all launch)
+      int gc0 = gz_c0;
+      refresh(gc0);
+#pragma unroll
+      for (int m = 0; m < GMAX; ++m) {
+        const int c = gc0 + m * NT;
+        if (c >= 2 * tw + 2 * th) continue;
+        int gx, gy;
+        if (ghost_cell(c, gx, gy) < 0) continue;
+        const int lg = (gy + 1) * rw + gx + 1;
+        const T xg = xs[lg];
+        const T xR = gx == tw ? x2[2 * tw + th + gy] : xs[lg + 1];
+        const T xL = gx == -1 ? x2[2 * tw + gy] : xs[lg - 1];
+        const T xD = gy == th ? x2[tw + gx] : xs[lg + rw];
+        const T xU = gy == -1 ? x2[gx] : xs[lg - rw];
+        const int u = ox + gx, v = oy + gy;
+        RowData r;
+        r.mu = gdat[c]; r.isn = gdat[perim + c]; r.zs = gdat[2 * perim + c]; r.isr = gdat[3 * perim + c];
+        r.gR = gdat[4 * perim + c]; r.sR = gdat[5 * perim + c]; r.gL = gdat[6 * perim + c];
+        r.sL = gdat[7 * perim + c]; r.gD = gdat[8 * perim + c]; r.sD = gdat[9 * perim + c];
+        r.gU = gdat[10 * perim + c]; r.sU = gdat[11 * perim + c];
+        const Row q = row_at(r, u, v, xg, xR, xL, xD, xU, true);
+        const T ig = q.d > (T)0 ? (T)1 / q.d : (T)0;
+        const T ax = q.d * xg - q.cr * xR - q.cl * xL - q.cd * xD - q.cu * xU;
+        ps[lg] = (q.bb - ax) * ig;
+      }
+    }
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
       if (lxy[j] < 0) continue;
       const int u = ox + KF_LX(j), v = oy + KF_LY(j);
       const int i = KF_GI(j), l = KF_LI(j);
       const T xi = xr[j];
-      const T mu = mu_g[i], isn = isn_g[i];
-      const T wn = postfit ? (T)0 : huber_w((xi - mu) * isn, delta, tukey) * isn * isn;
-      T zs;
-      const T isr = semi(i, zs);
-      T ws = (T)0;
-      if (isr > (T)0) ws = huber_w((xi - (T)tau - zs) * isr, delta, tukey) * isr * isr;
-      T bb = wn * mu + ws * ((T)tau + zs);
-      T cr = 0, cl = 0, cd = 0, cu = 0;
+      const T xR = xs[l + 1], xL = xs[l - 1], xD = xs[l + rw], xU = xs[l - rw];
+      const Row q = row_at(row_data(i, u, v), u, v, xi, xR, xL, xD, xU, !nopair);
       if (nopair) {
         // per-pixel weighted mean of the network and semi-dense log-depths
-        if (wn + ws > (T)0) xr[j] = bb / (wn + ws);
+        if (q.wn + q.ws > (T)0) xr[j] = q.bb / (q.wn + q.ws);
         continue;
       }
-      if (u < W - 1) {
-        const T g = gx_g[i];
-        cr = edge_weight(xi, xs[l + 1], g, isgx_g[i], delta, tukey);
-        bb -= cr * g;
-      }
-      if (u > 0) {
-        const T g = gx_g[i - 1];
-        cl = edge_weight(xs[l - 1], xi, g, isgx_g[i - 1], delta, tukey);
-        bb += cl * g;
-      }
-      if (v < H - 1) {
-        const T g = gy_g[i];
-        cd = edge_weight(xi, xs[l + rw], g, isgy_g[i], delta, tukey);
-        bb -= cd * g;
-      }
-      if (v > 0) {
-        const T g = gy_g[i - W];
-        cu = edge_weight(xs[l - rw], xi, g, isgy_g[i - W], delta, tukey);
-        bb += cu * g;
-      }
-      const T d = wn + ws + cr + cl + cd + cu;
-      dg[j] = d;
-      idg[j] = d > (T)0 ? (T)1 / d : (T)0;   // d = 0 only without network and gradient terms
-      cR[j] = cr; cL[j] = cl; cD[j] = cd; cU[j] = cu;
-      const T ax = d * xi - cr * xs[l + 1] - cl * xs[l - 1] - cd * xs[l + rw] - cu * xs[l - rw];
-      const T r = bb - ax;
+      dg[j] = q.d;
+      idg[j] = q.d > (T)0 ? (T)1 / q.d : (T)0;   // d = 0 only without network and gradient terms
+      cR[j] = q.cr; cL[j] = q.cl; cD[j] = q.cd; cU[j] = q.cu;
+      const T ax = q.d * xi - q.cr * xR - q.cl * xL - q.cd * xD - q.cu * xU;
+      const T r = q.bb - ax;
       rr[j] = r;
       const T z = r * idg[j];
       pv[j] = z;
       ps[l] = z;
       rz += (double)r * (double)z;
       r2 += (double)r * (double)r;
-      b2 += (double)bb * (double)bb;
+      b2 += (double)q.bb * (double)q.bb;
     }
     int it = 0;
     T qv[PPT];
     if (!nopair) {
-    vals[0] = rz; vals[1] = r2; vals[2] = b2;
-    if (!tm.sync(e++, tol_mode ? 3 : 1, vals, tot, gval, true, ps, true)) return;
-    double rz_t = tot[0];
-    const double bnorm = tol_mode ? sqrt(tot[2]) : 0.0;
+    double rz_t = 0.0, bnorm = 0.0;
+    if (ghost_z) {
+      __syncthreads();
+    } else {
+      vals[0] = rz; vals[1] = r2; vals[2] = b2;
+      if (!tm.sync(e++, tol_mode ? 3 : 1, vals, tot, gval, true, ps, true)) return;
+      rz_t = tot[0];
+      bnorm = tol_mode ? sqrt(tot[2]) : 0.0;
+    }
     bool converged = false;
     if (tol_mode) {
       relres = bnorm > 0.0 ? sqrt(tot[1]) / bnorm : 0.0;
@@ -639,7 +899,7 @@ __device__ __forceinline__ void solve_member(const SolveArgs& a, const int b, un
           }
         };
         // the neighbours' m lands directly in the ghost ring of mring
-        if (!tm.sync(e++, 2, vals, tot, gval, true, mring, true, interior)) return;
+        if (!tm.template sync<false>(e++, 2, vals, tot, gval, true, mring, true, interior)) return;
         if (tot[0] == 0.0) break;
         double beta = 0.0, den = tot[1];
         if (i > 0) {
@@ -753,10 +1013,22 @@ __device__ __forceinline__ void solve_member(const SolveArgs& a, const int b, un
       xs[KF_LI(j)] = xr[j];
     }
     vals[0] = num; vals[1] = den; vals[2] = cnt;
-    // the neighbours' x lands directly in the ghost ring of xs
-    if (!tm.sync(e++, 3, vals, tot, gval, true, xs, true)) return;
+    // the neighbours' x lands directly in the ghost ring of xs (with
+    // ghost_z also its second ring and corners); the count of pixels with a
+    // semi-dense measurement does not change over the GN iterations, so only
+    // the first scale step reduces it
+    const int nv_scale = gn == 0 ? 3 : 2;
+    if constexpr (PIPE) {
+      const uint32_t es = e;
+      auto pub2 = [&] {
+        if (ghost_z) tm.publish_ring2(es, xs);
+      };
+      if (!tm.template sync<true>(e++, nv_scale, vals, tot, gval, true, xs, true, pub2)) return;
+    } else {
+      if (!tm.sync(e++, nv_scale, vals, tot, gval, true, xs, true)) return;
+    }
     if (!postfit && tot[1] > 0.0) tau = tot[0] / tot[1];
-    n_valid = tot[2];
+    if (gn == 0) n_valid = tot[2];
   }
   if (postfit && !new_kf) {
     // least-squares fit of the log-scale to the network: tau = mean(mu - y)
@@ -867,7 +1139,8 @@ namespace {
 
 size_t smem_for(size_t elt, const Tiling& t) {
   const size_t ring = (size_t)(t.tile_h + 2) * (t.tile_w + 2);
-  return sizeof(double) * ((size_t)(t.threads / 64) * NV_MAX + NV_MAX * (MAX_TEAM / 64) + 2) + 3 * ring * elt;
+  const size_t ring2 = 2 * (size_t)t.tile_w + 2 * (size_t)t.tile_h;
+  return sizeof(double) * ((size_t)(t.threads / 64) * NV_MAX + NV_MAX * (MAX_TEAM / 64) + 2) + (3 * ring + 13 * ring2) * elt;
 }
 
 template <typename T, bool PIPE, bool VAR>

@@ -223,6 +223,40 @@ def test_solver_ragged_tiles(c0):
     assert err.max() <= 1e-10 and abs(st["tau"] - tau_o) <= 1e-10
 
 
+@pytest.mark.parametrize("precision,tiles", [("f64", (54, 4)), ("f64", (14, 18)), ("f32", (54, 4)),
+                                             ("f32", (14, 18))])
+def test_solver_two_deep_boundary_ragged(c0, precision, tiles):
+    """Fixed-count pipelined CG assembles the ghost values of its first stencil
+    operand from x shipped two pixels deep (no initial-residual
+    synchronisation). 54 x 4 tiles of 160 x 120: tiles 3 px wide, the last
+    column 1 px wide (its left neighbour's second ring to the right lies
+    outside the image); 14 x 18: tiles 7 px high, the last row 1 px high. Both
+    against the oracle's iteration-matched solve."""
+    gu.say(f"[solver-2deep] config 0 case 0 {precision} tiles {tiles}")
+    rho, var = _oracle_state(c0)
+    dt = gu.np_map_dtype(precision)
+    rho_in, var_in = rho.astype(dt), var.astype(dt)
+    kf = gu.make_gpu_kf(c0, precision, "line5", 32, n_gn=3, n_cg=15, tiles=tiles, solver_threads=256,
+                        cg_variant="pipelined")
+    mdt = gu.map_dtype(precision)
+    kf.import_state(rho=gu.dev(rho_in, mdt), var=gu.dev(var_in, mdt))
+    kf.solve()
+    s = kf.stats()
+    st = kf.export_state()
+    prior = gu.rounded_priors(c0, precision)
+    semi = gu.oracle_semi(rho_in.astype(np.float64), var_in.astype(np.float64))
+    x_o, tau_o, _ = fusion.gauss_newton(prior.mu, 0.0, prior, semi,
+                                        SolverParams(n_gn=3, n_cg=15, linear_solver="pcg"))
+    err = np.abs(st["x"].cpu().numpy().astype(np.float64) - x_o)
+    gu.say(f"[solver-2deep] max|dx| {err.max():.3e} rms {np.sqrt(np.mean(err ** 2)):.3e} "
+           f"dtau {abs(st['tau'] - tau_o):.3e} syncs {s.team_syncs}")
+    assert s.team_syncs == 3 * (15 + 1)   # per GN iteration: the CG iterations and the scale step
+    if precision == "f64":
+        assert err.max() <= 1e-10 and abs(st["tau"] - tau_o) <= 1e-10
+    else:
+        assert err.max() <= 2e-4 and np.sqrt(np.mean(err ** 2)) <= 2e-5 and abs(st["tau"] - tau_o) <= 2e-5
+
+
 def test_prior_only_returns_prior_gpu():
     """P1 on the GPU: texture-free keyframe (S empty) and g = forward difference of mu."""
     case = kfsynth.make_case(77, 96, 64, 1)

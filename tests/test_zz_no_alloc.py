@@ -46,8 +46,8 @@ def test_fuse_frame_static_equals_fuse_frame(precision, pattern, ns):
 def test_fuse_frame_static_rejects_oversized_keyframes():
     """A valid keyframe whose scratch exceeds the static array: 8000 x 96 with an
     explicit 8 x 32 tiling at 1024 threads (tiles of 1000 x 3 px, so 256 tile
-    boundaries of 2006 slots: ~16 MB of exchange words) is refused before any
-    device work, and the context stays usable."""
+    boundaries of 2 x 2006 slots: ~33 MB of exchange words) is refused before
+    any device work, and the context stays usable."""
     from paper_2207_12244_amd import kf as K
     from paper_2207_12244_amd.kf import Keyframe
     t = gu.torch()
