@@ -7,9 +7,9 @@
 // samples share four of their five points when the step is 1 px) and k = l,
 // l + G, ... for the 5 x 5 patch. The keyframe pattern (5 or 25 values) is
 // evaluated once per pixel and handed to every lane of the group by cross-lane
-// broadcasts; the argmin over the N_s SSDs is a butterfly of cross-lane
-// shuffles inside the group with ties resolved to the smaller k. No LDS, no
-// barriers.
+// broadcasts when the group has a lane per point, otherwise by every lane;
+// the argmin over the N_s SSDs is a butterfly of cross-lane shuffles inside
+// the group with ties resolved to the smaller k. No LDS, no barriers.
 #include "kf_internal.h"
 
 namespace kf {
@@ -19,19 +19,19 @@ namespace {
 constexpr int ST_THREADS = 256;
 constexpr int ST_WAVES = ST_THREADS / 64;
 
-// Lanes of a wavefront that share one textured pixel: 16 samples per lane for
-// the 5-point line pattern (whose consecutive samples share points) and about
-// 4 for the 25-point patch, so that the per-pixel work (geometry, argmin,
-// sub-pixel step, filter), which every lane of the group repeats, is spread
-// over several pixels per wavefront; at least 32 lanes for the 25-point
-// pattern, so that each of its points is evaluated by one lane and broadcast.
-// Any split gives the same argmin (a lexicographic (SSD, k) minimum) of the
-// same SSDs.
-constexpr int lanes_per_pixel(int pat, int ns) {
-  const int per = pat == KF_PAT_LINE5 ? 16 : 4;
-  int g = ns / per < 1 ? 1 : (ns / per > 64 ? 64 : ns / per);
-  if (pat == KF_PAT_SQ5X5 && g < 32) g = ns < 32 ? ns : 32;
-  return g;
+// Lanes of a wavefront that share one textured pixel: N_s / 16, i.e. 16
+// samples per lane, for both patterns. The per-pixel work (geometry, argmin,
+// sub-pixel step, filter, and for the 25-point patch below 25 lanes the
+// keyframe pattern itself) is repeated by every lane of the group, so smaller
+// groups do less of it per pixel; 16 samples per lane is where the lane's own
+// sample registers still fit. Measured per 640 x 480 frame: SQ5X5 at N_s =
+// 32 / 64 / 128 takes 63 / 93 / 138 us (f32) with 2 / 4 / 8 lanes, against
+// 134 / 141 / 156 us with 32 lanes and 229 us with 4 lanes at N_s = 128; LINE5
+// at N_s = 32 and 64 is slower with half or twice its group. The argmin is a
+// lexicographic (SSD, k) minimum, so the split only changes which lane
+// evaluates a sample.
+constexpr int lanes_per_pixel(int, int ns) {
+  return ns / 16 < 1 ? 1 : (ns / 16 > 64 ? 64 : ns / 16);
 }
 
 template <typename T>
