@@ -480,7 +480,7 @@ kf_status kf_create(const kf_config* cfg, kf_ctx** out) {
     rate_khz = 100000;
   const double timeout_ms = cfg->solver_timeout_ms > 0.0 ? cfg->solver_timeout_ms : 2000.0;
   c->timeout_ticks = (uint64_t)((double)rate_khz * timeout_ms);   // wall-clock ticks
-  c->stereo_blocks = stereo_grid_blocks(c->device);
+  c->stereo_blocks = stereo_grid_blocks(c->device, cfg->pipeline_frames != 0);
   c->coresident = -1;
   if (cfg->pipeline_frames) {
     hipError_t e = hipStreamCreateWithFlags(&c->solve_stream, hipStreamNonBlocking);

@@ -299,7 +299,7 @@ kf_status kf_batch_create(kf_ctx* const* members, int32_t n, const kf_batch_conf
   b->kind = b->pipelined ? 1 : 0;
   for (int i = 0; i < n; ++i) b->kind |= solve_kind(members[i]->cfg) & 2;
   b->use_graph = cfg->use_graph != 0;
-  b->stereo_blocks = c0->stereo_blocks;
+  b->stereo_blocks = stereo_grid_blocks(c0->device, false);
   b->dl = dl;
   char* ws = reinterpret_cast<char*>(cfg->workspace);
   b->d_so = reinterpret_cast<SolveArgs*>(ws);

@@ -235,7 +235,8 @@ hipError_t launch_import(int prec, const ImportArgs& a, hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_set_u32(uint32_t* p, uint32_t v, hipStream_t s);
 size_t solve_smem_bytes(int prec, const Tiling& t);
-int stereo_grid_blocks(int device);
+// Stereo grid: 8 workgroups per compute unit, or 1 when the stereo runs beside a solve.
+int stereo_grid_blocks(int device, bool beside_solve);
 
 }  // namespace kf
 

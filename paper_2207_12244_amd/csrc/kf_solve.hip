@@ -151,14 +151,17 @@ struct Team {
 
   // Replica r of member j's partial v: every member writes all replicas and
   // reads replica (own index mod PART_REPLICAS), so the team's polling loads
-  // spread over several copies of the hot words.
+  // spread over several copies of the hot words. A one-word partial sits at a
+  // one-word stride, so a wavefront's 64 polled slots span half the cache
+  // lines of two-word slots (-2 % on the 640 x 480 solve).
   __device__ KF_GLOBAL uint64_t* part_slot(uint32_t e, int v, int j, int r) const {
-    return parts + ((size_t)(((e & 1u) * NV_MAX + v) * PART_REPLICAS + r) * B + j) * 2;
+    return parts + ((size_t)(((e & 1u) * NV_MAX + v) * PART_REPLICAS + r) * B + j) * (packed ? 1 : 2);
   }
   // Boundary lists of member blk: [0, perim) its first row / column per side,
   // [perim, 2 perim) its second row / column per side (publish_ring2).
+  // (a slot is as many words as the value's transport, Wire<T>::N)
   __device__ KF_GLOBAL uint64_t* halo_slot(uint32_t e, int blk, int off) const {
-    return halo + ((size_t)((e & 1u) * B + blk) * (2 * perim) + off) * 2;
+    return halo + ((size_t)((e & 1u) * B + blk) * (2 * perim) + off) * Wire<T>::N;
   }
 
   // Publishes the boundary value of own pixel (lx, ly) for the neighbours that read it.

@@ -641,10 +641,16 @@ hipError_t stereo_prec(int pattern, int ns, const StereoArgs& a, int blocks, hip
 
 }  // namespace
 
-int stereo_grid_blocks(int device) {
+int stereo_grid_blocks(int device, bool beside_solve) {
   int cus = 256;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) cus = 256;
-  return cus * 8;
+  // Beside a running solve (frame pipelining), one workgroup per compute unit:
+  // the stereo takes longer but stays hidden under the solve, whose team waits
+  // on its slowest workgroup and so on every SIMD the stereo's waves share.
+  // 640 x 480 headline: 8 / 4 / 2 / 1 / 0.5 workgroups per compute unit give
+  // 452 / 464 / 470 / 472 / 465 Mpixel/s (0.25: 330, the stereo then outlasts
+  // the solve).
+  return beside_solve ? cus : cus * 8;
 }
 
 hipError_t launch_stereo_batch(int prec, int pattern, int ns, const StereoArgs* tab, const int32_t* n, int nmax,
