@@ -2,6 +2,7 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
     python bench.py --sync-sweep      (team-synchronisation latency vs team size)
+    python bench.py --accuracy        (depth accuracy of the method's variants, synthetic scenes)
 
 Workload (default): one 640 x 480 keyframe fused with a 30-frame sequence in the
 precision form (bf16 keyframe image and patch buffers, fp32 maps and arithmetic,
@@ -668,6 +669,58 @@ def run_sync_sweep(torch, rounds=2000, threads=512):
                      "the fastest of 3 launches timed with HIP events, after one warm-up launch"}
 
 
+# accuracy of the method's variants on the synthetic headline scenes: the
+# share of depth values within 10 % of the ground truth (Sec. III's measure)
+ACCURACY_CASES = (0, 1, 2)
+ACCURACY_VARIANTS = (
+    ("network prior only", None),
+    ("full cost, Huber", {}),
+    ("full cost, Tukey (c = 4.685)", dict(robust="tukey", huber_delta=4.685)),
+    ("no pairwise terms (Table III)", dict(variant="no_pairwise")),
+    ("least-squares scale post-fit (Table II)", dict(variant="scale_postfit")),
+)
+
+
+def run_accuracy(torch):
+    """Each variant fuses the 30-frame 640 x 480 headline sequence (precision
+    form, SQ5X5, N_s = 128, 10 x 20) of three seeded synthetic scenes; the
+    fused depth is compared with the rendered ground truth of the keyframe.
+    "network prior only" reads the depth right after the keyframe is set."""
+    import kfsynth
+    from paper_2207_12244_amd.kf import Keyframe
+    wl = WORKLOAD
+    dev = lambda x, dt: torch.as_tensor(np.ascontiguousarray(x), dtype=dt, device="cuda")
+    per = {name: [] for name, _ in ACCURACY_VARIANTS}
+    for c in ACCURACY_CASES:
+        case = kfsynth.config_case(wl["config"], c)
+        gt = case.depth0.astype(np.float64)
+        img0 = dev(case.image0, torch.uint8)
+        priors = [dev(m, torch.float32) for m in case.priors.maps()]
+        frames = [dev(im, torch.uint8) for im in case.images]
+        for name, kw in ACCURACY_VARIANTS:
+            kf = Keyframe(case.W, case.H, precision=wl["precision"], pattern=wl["pattern"], n_samples=wl["n_samples"],
+                          n_gn=wl["n_gn"], n_cg=wl["n_cg"], K=case.K, **(kw or {}))
+            kf.set_prior(img0, *priors, case.T_wc0)
+            if kw is not None:
+                for f, im in enumerate(frames):
+                    kf.fuse_frame(im, case.poses[f])
+            d, _ = kf.read_depth()
+            kf.close()
+            rel = np.abs(d.cpu().numpy().astype(np.float64) - gt) / gt
+            per[name].append({"case": c, "pct_within_10": round(100.0 * float(np.mean(rel < 0.1)), 2),
+                              "mean_abs_rel": round(float(np.mean(rel)), 4)})
+            print(f"# accuracy case {c} {name}: {per[name][-1]}", file=sys.stderr, flush=True)
+    out = {}
+    for name, rows in per.items():
+        out[name] = {"pct_within_10": round(float(np.mean([r["pct_within_10"] for r in rows])), 2),
+                     "mean_abs_rel": round(float(np.mean([r["mean_abs_rel"] for r in rows])), 4), "per_case": rows}
+    return {"accuracy_synthetic": out,
+            "workload": f"{len(ACCURACY_CASES)} seeded synthetic 640x480 scenes (config 2 cases "
+                        f"{list(ACCURACY_CASES)}), 30 frames each, {wl['precision']} form, {wl['pattern']}, "
+                        f"N_s={wl['n_samples']}, {wl['n_gn']} GN x {wl['n_cg']} PCG; ground truth = rendered "
+                        "keyframe depth; measure = share of pixels with |d - d_gt| / d_gt < 0.1"}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -684,6 +737,8 @@ def main(argv=None):
     ap.add_argument("--serving-tiles", default="auto", choices=["tuned", "auto"],
                     help="serving tile shapes: latency-optimal per size (auto) or the batch autotuner's")
     ap.add_argument("--batched-steps", type=int, default=10)
+    ap.add_argument("--accuracy", action="store_true",
+                    help="only the depth accuracy of the method's variants on synthetic scenes")
     ap.add_argument("--sync-sweep", action="store_true",
                     help="only measure the team-synchronisation latency against team size (kf_probe_sync)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -695,6 +750,13 @@ def main(argv=None):
               file=sys.stderr)
         return 2
 
+    if a.accuracy:
+        import torch
+        if not torch.cuda.is_available():
+            print("bench.py needs a GPU", file=sys.stderr)
+            return 2
+        print(json.dumps(run_accuracy(torch)), flush=True)
+        return 0
     if a.sync_sweep:
         import torch
         if not torch.cuda.is_available():

@@ -248,7 +248,7 @@ kf_status kf_read_depth(kf_ctx* ctx, void* depth_out, void* var_out, double* sca
    context's workspace. Allocates nothing and calls no allocating routine.
    KF_ERR_ARG if the keyframe needs more scratch than the array holds
    ((height + 1) x row stride of the staged frame, rows padded to a multiple of
-   64 bytes >= width + 8, plus the exchange words: 640 x 480 needs 1.7 MB);
+   64 bytes >= width + 8, plus the exchange words: 640 x 480 needs 2.8 MB);
    KF_ERR_STATE before kf_set_prior or with pipeline_frames. Every call on a
    device shares that device's array and clears what must start at zero, so
    calls that overlap on one device (contexts on different streams) race. */
