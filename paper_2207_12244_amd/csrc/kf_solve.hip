@@ -1058,7 +1058,11 @@ __device__ __forceinline__ void solve_member(const SolveArgs& a, const int b, un
   if (b == 0 && tid == 0) {
     // every member has read e0 before its first publish, and workgroup 0
     // passed the last synchronisation, so no member still needs the old base
-    scal->epoch = e0 + a.epoch_span;
+    // a launch that made no synchronisation (new keyframe) keeps the base:
+    // then every exchange slot's last write stays within one launch span of
+    // its next poll, whatever runs of such launches occur, which the 16-bit
+    // tags of one-word partials rely on
+    scal->epoch = e0 + (e != e0 ? a.epoch_span : 0u);
     scal->tau = tau;
     scal->cg_iterations = cg_total;
     scal->cg_rel_residual = relres;
