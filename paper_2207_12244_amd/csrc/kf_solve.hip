@@ -129,7 +129,6 @@ struct Team {
   static constexpr int CPV = MAX_TEAM / 64;                            // 64-slot chunks per value, at most
   int B, b, tw, th, rw, perim, tile_w, tile_h;
   int nb_up, nb_dn, nb_lf, nb_rt;
-  int tiles_x;
   KF_GLOBAL uint64_t* parts;
   KF_GLOBAL uint64_t* halo;
   KF_GLOBAL int32_t* err;
@@ -462,7 +461,6 @@ __device__ __forceinline__ void team_init(Team<T, NT>& tm, MemberLds<T, NT>& lds
   tm.nb_dn = by < a.tiles_y - 1 ? b + a.tiles_x : -1;
   tm.nb_lf = bx > 0 ? b - 1 : -1;
   tm.nb_rt = bx < a.tiles_x - 1 ? b + 1 : -1;
-  tm.tiles_x = a.tiles_x;
   tm.parts = gp(a.parts);
   tm.halo = gp(a.halo);
   tm.err = &gp(a.scal)->err;
