@@ -257,6 +257,49 @@ def test_solver_two_deep_boundary_ragged(c0, precision, tiles):
         assert err.max() <= 2e-4 and np.sqrt(np.mean(err ** 2)) <= 2e-5 and abs(st["tau"] - tau_o) <= 2e-5
 
 
+def _random_tilings(n, seed=2207):
+    """Seeded (W, H, tiles_x, tiles_y) with tiles of at least 2 x 2 px, no empty
+    tile, at most 256 tiles and a second ring that fits one slot per thread of a
+    256-thread workgroup: the conditions under which the pipelined solve
+    assembles its ghost rows from x shipped two pixels deep."""
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < n:
+        W, H = int(rng.integers(40, 201)), int(rng.integers(30, 151))
+        tx, ty = int(rng.integers(1, 17)), int(rng.integers(1, 17))
+        tw, th = -(-W // tx), -(-H // ty)
+        if tx * ty > 256 or (tx - 1) * tw >= W or (ty - 1) * th >= H or tw < 2 or th < 2:
+            continue
+        if 2 * (tw + th) + 4 > 256 or tw * th > 256 * 6:
+            continue
+        out.append((W, H, tx, ty))
+    return out
+
+
+@pytest.mark.parametrize("W,H,tx,ty", _random_tilings(6))
+def test_solver_two_deep_boundary_random_tilings(W, H, tx, ty):
+    """The two-deep exchange on seeded random sizes and tilings (ragged last
+    rows and columns of tiles included), FP64 pipelined 3 x 15 against the
+    oracle's iteration-matched solve."""
+    gu.say(f"[solver-2deep-random] {W}x{H} tiles {tx}x{ty} f64")
+    case = kfsynth.make_case(7000 + W * 1000 + H, W, H, 1)
+    rho, var = _oracle_state(case)
+    kf = gu.make_gpu_kf(case, "f64", "line5", 32, n_gn=3, n_cg=15, tiles=(tx, ty), solver_threads=256,
+                        cg_variant="pipelined")
+    t = gu.torch()
+    kf.import_state(rho=gu.dev(rho, t.float64), var=gu.dev(var, t.float64))
+    kf.solve()
+    s = kf.stats()
+    st = kf.export_state()
+    prior = gu.rounded_priors(case, "f64")
+    x_o, tau_o, _ = fusion.gauss_newton(prior.mu, 0.0, prior, gu.oracle_semi(rho, var),
+                                        SolverParams(n_gn=3, n_cg=15, linear_solver="pcg"))
+    err = np.abs(st["x"].cpu().numpy() - x_o)
+    gu.say(f"[solver-2deep-random] max|dx| {err.max():.3e} dtau {abs(st['tau'] - tau_o):.3e} syncs {s.team_syncs}")
+    assert s.team_syncs == 3 * (15 + 1)
+    assert err.max() <= 1e-10 and abs(st["tau"] - tau_o) <= 1e-10
+
+
 def test_prior_only_returns_prior_gpu():
     """P1 on the GPU: texture-free keyframe (S empty) and g = forward difference of mu."""
     case = kfsynth.make_case(77, 96, 64, 1)
