@@ -192,7 +192,9 @@ char* var_buf(kf_ctx* c, int b) { return c->ws + (b ? c->lay.var2 : c->lay.var);
 // solve stream (they run in order, so waiting for the last one suffices).
 hipError_t wait_solves(kf_ctx* c) {
   if (c->last_solve < 0) return hipSuccess;
-  return hipStreamWaitEvent(c->stream, c->ev_solve[c->last_solve], 0);
+  const hipError_t e = hipStreamWaitEvent(c->stream, c->ev_solve[c->last_solve], 0);
+  if (e == hipSuccess) c->solves_waited = true;
+  return e;
 }
 
 // General 4x4 inverse (Gauss-Jordan, partial pivoting), row-major.
@@ -480,12 +482,16 @@ kf_status kf_create(const kf_config* cfg, kf_ctx** out) {
     rate_khz = 100000;
   const double timeout_ms = cfg->solver_timeout_ms > 0.0 ? cfg->solver_timeout_ms : 2000.0;
   c->timeout_ticks = (uint64_t)((double)rate_khz * timeout_ms);   // wall-clock ticks
-  c->stereo_blocks = stereo_grid_blocks(c->device, cfg->pipeline_frames != 0);
+  c->stereo_blocks = stereo_grid_blocks(c->device, false);
+  c->stereo_blocks_beside = stereo_grid_blocks(c->device, true);
   c->coresident = -1;
   if (cfg->pipeline_frames) {
+    // the two streams' events order work on this device only (the host reads
+    // results through the user stream), so they skip the system-scope fence
+    const unsigned ev_flags = hipEventDisableTiming | hipEventDisableSystemFence;
     hipError_t e = hipStreamCreateWithFlags(&c->solve_stream, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_user, hipEventDisableTiming);
-    for (int b = 0; b < 2 && e == hipSuccess; ++b) e = hipEventCreateWithFlags(&c->ev_solve[b], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_user, ev_flags);
+    for (int b = 0; b < 2 && e == hipSuccess; ++b) e = hipEventCreateWithFlags(&c->ev_solve[b], ev_flags);
     if (e != hipSuccess) {
       (void)hipGetLastError();
       kf_destroy(c);
@@ -630,8 +636,10 @@ kf_status kf_stereo_update(kf_ctx* c, const uint8_t* image1, const double T_wc1[
     a.buf = nxt;
     if (c->solve_pending[nxt]) e = hipStreamWaitEvent(c->stream, c->ev_solve[nxt], 0);
   }
-  if (e == hipSuccess)
-    e = launch_stereo(c->cfg.precision, c->cfg.pattern, c->cfg.n_samples, a, c->stereo_blocks, c->stream);
+  // beside a solve still in flight the update takes one workgroup per compute
+  // unit; with none in flight (the user stream waited for them all) the full grid
+  const int blocks = c->cfg.pipeline_frames && !c->solves_waited ? c->stereo_blocks_beside : c->stereo_blocks;
+  if (e == hipSuccess) e = launch_stereo(c->cfg.precision, c->cfg.pattern, c->cfg.n_samples, a, blocks, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "kf_stereo_update");
   if (c->cfg.pipeline_frames) c->cur = nxt;
   ++c->frame;
@@ -669,6 +677,7 @@ kf_status kf_solve(kf_ctx* c) {
     e = hipEventRecord(c->ev_solve[c->cur], s);
     c->solve_pending[c->cur] = true;
     c->last_solve = c->cur;
+    c->solves_waited = false;
   }
   if (e != hipSuccess) return hip_fail(c, e, "kf_solve");
   c->epoch += bound;

@@ -254,7 +254,8 @@ struct kf_ctx {
   std::string err;
   char* ws;
   uint64_t timeout_ticks;
-  int stereo_blocks;
+  int stereo_blocks;          // stereo grid alone on the device
+  int stereo_blocks_beside;   // and beside a solve (frame pipelining)
   int coresident;      // workgroups of the solver tiling the device holds at once (-1: not checked)
   // frame pipelining (cfg.pipeline_frames): the solve runs on solve_stream, the
   // filter state alternates between two buffers, cur = the one the last stereo
@@ -265,6 +266,7 @@ struct kf_ctx {
   hipEvent_t ev_solve[2] = {nullptr, nullptr};   // last solve that read buffer b
   bool solve_pending[2] = {false, false};
   int last_solve = -1;                    // buffer of the last enqueued solve
+  bool solves_waited = true;              // the user stream waits for every enqueued solve
 };
 
 namespace kf {
