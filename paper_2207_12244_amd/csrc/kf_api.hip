@@ -482,8 +482,7 @@ kf_status kf_create(const kf_config* cfg, kf_ctx** out) {
     rate_khz = 100000;
   const double timeout_ms = cfg->solver_timeout_ms > 0.0 ? cfg->solver_timeout_ms : 2000.0;
   c->timeout_ticks = (uint64_t)((double)rate_khz * timeout_ms);   // wall-clock ticks
-  c->stereo_blocks = stereo_grid_blocks(c->device, false);
-  c->stereo_blocks_beside = stereo_grid_blocks(c->device, true);
+  c->cus = device_cus(c->device);
   c->coresident = -1;
   if (cfg->pipeline_frames) {
     // the two streams' events order work on this device only (the host reads
@@ -638,8 +637,8 @@ kf_status kf_stereo_update(kf_ctx* c, const uint8_t* image1, const double T_wc1[
   }
   // beside a solve still in flight the update takes one workgroup per compute
   // unit; with none in flight (the user stream waited for them all) the full grid
-  const int blocks = c->cfg.pipeline_frames && !c->solves_waited ? c->stereo_blocks_beside : c->stereo_blocks;
-  if (e == hipSuccess) e = launch_stereo(c->cfg.precision, c->cfg.pattern, c->cfg.n_samples, a, blocks, c->stream);
+  const bool beside = c->cfg.pipeline_frames && !c->solves_waited;
+  if (e == hipSuccess) e = launch_stereo(c->cfg.precision, c->cfg.pattern, c->cfg.n_samples, a, c->cus, beside, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "kf_stereo_update");
   if (c->cfg.pipeline_frames) c->cur = nxt;
   ++c->frame;
@@ -761,7 +760,7 @@ kf_status kf_fuse_frame_static(kf_ctx* c, const uint8_t* image1, const double T_
   // the array holds whatever the last call on this device left: its exchange
   // words start from zero (epoch 0 is never used), cleared by a fill kernel
   if (e == hipSuccess) e = launch_zero(base + stage, exch, c->stream);
-  if (e == hipSuccess) e = launch_stereo(g.precision, g.pattern, g.n_samples, a, c->stereo_blocks, c->stream);
+  if (e == hipSuccess) e = launch_stereo(g.precision, g.pattern, g.n_samples, a, c->cus, false, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "kf_fuse_frame_static (stereo)");
   ++c->frame;
   SolveArgs sa;

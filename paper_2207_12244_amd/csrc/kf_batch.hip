@@ -51,7 +51,7 @@ struct kf_batch {
   int grid = 0;                    // solver workgroups
   int max_queue = 0;               // longest per-workgroup queue of the last schedule
   int capacity = 0;                // co-resident workgroups of the batched solver
-  int stereo_blocks = 0;
+  int cus = 256;   // compute units of the device (stereo grid)
   bool use_graph = true;
   DynLayout dl{};
   char* d_dyn = nullptr;           // device: per-call region
@@ -152,7 +152,7 @@ void schedule(kf_batch* b, const std::vector<int>& active) {
 hipError_t enqueue(kf_batch* b, int which, hipStream_t s) {
   hipError_t e = hipSuccess;
   if (which != 2)
-    e = launch_stereo_batch(b->prec, b->pattern, b->ns, b->d_st(), b->d_n(), (int)b->m.size(), b->stereo_blocks, s);
+    e = launch_stereo_batch(b->prec, b->pattern, b->ns, b->d_st(), b->d_n(), (int)b->m.size(), b->cus, s);
   if (e == hipSuccess && which != 1)
     e = launch_solve_batch(b->prec, b->threads, b->ppt, b->kind, b->d_so, b->d_queue(), b->d_qoff(), b->grid,
                            b->smem, s);
@@ -299,7 +299,7 @@ kf_status kf_batch_create(kf_ctx* const* members, int32_t n, const kf_batch_conf
   b->kind = b->pipelined ? 1 : 0;
   for (int i = 0; i < n; ++i) b->kind |= solve_kind(members[i]->cfg) & 2;
   b->use_graph = cfg->use_graph != 0;
-  b->stereo_blocks = stereo_grid_blocks(c0->device, false);
+  b->cus = device_cus(c0->device);
   b->dl = dl;
   char* ws = reinterpret_cast<char*>(cfg->workspace);
   b->d_so = reinterpret_cast<SolveArgs*>(ws);

@@ -215,11 +215,14 @@ struct ImportArgs {
 
 hipError_t launch_prior(int prec, const PriorArgs& a, hipStream_t s);
 hipError_t launch_resample_priors(int prec, const ResampleArgs& a, hipStream_t s);
-hipError_t launch_stereo(int prec, int pattern, int ns, const StereoArgs& a, int blocks, hipStream_t s);
+// Staging + stereo update of one keyframe on `cus` compute units: as many
+// workgroups as the device holds at once, or one per unit beside a running solve.
+hipError_t launch_stereo(int prec, int pattern, int ns, const StereoArgs& a, int cus, bool beside_solve,
+                         hipStream_t s);
 // Batched stereo: the active count *n (device, <= nmax) and the table entries
 // are read by the kernels, so the launches can be captured once.
 hipError_t launch_stereo_batch(int prec, int pattern, int ns, const StereoArgs* tab, const int32_t* n, int nmax,
-                               int blocks, hipStream_t s);
+                               int cus, hipStream_t s);
 hipError_t launch_solve(int prec, const Tiling& t, const SolveArgs& a, bool cooperative, int kind, hipStream_t s);
 // Batched solver: workgroup g runs the team members queue[qoff[g] .. qoff[g+1])
 // in order, each entry (keyframe << 8) | member; all `grid` workgroups must be
@@ -235,8 +238,8 @@ hipError_t launch_import(int prec, const ImportArgs& a, hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_set_u32(uint32_t* p, uint32_t v, hipStream_t s);
 size_t solve_smem_bytes(int prec, const Tiling& t);
-// Stereo grid: 8 workgroups per compute unit, or 1 when the stereo runs beside a solve.
-int stereo_grid_blocks(int device, bool beside_solve);
+// Compute units of the device (256 if the query fails).
+int device_cus(int device);
 
 }  // namespace kf
 
@@ -254,8 +257,7 @@ struct kf_ctx {
   std::string err;
   char* ws;
   uint64_t timeout_ticks;
-  int stereo_blocks;          // stereo grid alone on the device
-  int stereo_blocks_beside;   // and beside a solve (frame pipelining)
+  int cus;                    // compute units of the device (stereo grids)
   int coresident;      // workgroups of the solver tiling the device holds at once (-1: not checked)
   // frame pipelining (cfg.pipeline_frames): the solve runs on solve_stream, the
   // filter state alternates between two buffers, cur = the one the last stereo

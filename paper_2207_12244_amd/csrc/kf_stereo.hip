@@ -10,6 +10,8 @@
 // broadcasts when the group has a lane per point, otherwise by every lane;
 // the argmin over the N_s SSDs is a butterfly of cross-lane shuffles inside
 // the group with ties resolved to the smaller k. No LDS, no barriers.
+#include <type_traits>
+
 #include "kf_internal.h"
 
 namespace kf {
@@ -93,6 +95,24 @@ __device__ inline void taps6(const KF_GLOBAL uint8_t* p, T* t) {
   t[3] = (T)(lo >> 24);
   t[4] = (T)(hi & 0xffu);
   t[5] = (T)((hi >> 8) & 0xffu);
+}
+
+// Five consecutive bf16 elements of the keyframe image from element index e
+// on, as floats, from the three aligned dwords that hold them: one dword load
+// per two elements instead of one load each. The image is followed by more
+// workspace, so the dword that holds its last element is in bounds.
+__device__ inline void row5_bf16(const KF_GLOBAL bf16* img, size_t e, float* t) {
+  const KF_GLOBAL uint32_t* w = (const KF_GLOBAL uint32_t*)(img + (e & ~(size_t)1));
+  const uint32_t sh = (uint32_t)(e & 1) * 2u;
+  const uint32_t w0 = w[0], w1 = w[1], w2 = w[2];
+  const uint32_t lo = __builtin_amdgcn_alignbyte(w1, w0, sh);
+  const uint32_t mid = __builtin_amdgcn_alignbyte(w2, w1, sh);
+  const uint32_t hi = __builtin_amdgcn_alignbyte(w2, w2, sh);   // low half: element e + 4
+  t[0] = __uint_as_float(lo << 16);
+  t[1] = __uint_as_float(lo & 0xffff0000u);
+  t[2] = __uint_as_float(mid << 16);
+  t[3] = __uint_as_float(mid & 0xffff0000u);
+  t[4] = __uint_as_float(hi << 16);
 }
 
 // Same for the resident keyframe image (storage type TI).
@@ -202,16 +222,51 @@ __device__ inline PixelGeom<T> pixel_geometry(const StereoArgs& a, T u, T v, T r
   return g;
 }
 
-// Position and inverse depth of sample k.
+// Position of sample k in image 1.
 template <typename T, int NS>
-__device__ inline void sample_pos(const PixelGeom<T>& g, const FrameConst& c, int k, T& px, T& py, T& rk) {
+__device__ inline void sample_xy(const PixelGeom<T>& g, int k, T& px, T& py) {
   const T off = (T)k - (T)((NS - 1) * 0.5);
   px = g.cx + off * g.h * g.lx;
   py = g.cy + off * g.h * g.ly;
+}
+
+// Inverse depth at image-1 position (px, py) of the pixel's ray, as the
+// quotient num / den of the coordinate the geometry solves from.
+template <typename T>
+__device__ inline void depth_ratio(const PixelGeom<T>& g, const FrameConst& c, T px, T py, T& num, T& den) {
   const T pm = g.use_x ? px : py;
   const T Am = g.use_x ? g.A0 : g.A1;
   const T bm = g.use_x ? (T)c.b[0] : (T)c.b[1];
-  rk = (pm * g.A2 - Am) / (bm - pm * (T)c.b[2]);
+  num = pm * g.A2 - Am;
+  den = bm - pm * (T)c.b[2];
+}
+
+// Position and inverse depth of sample k.
+template <typename T, int NS>
+__device__ inline void sample_pos(const PixelGeom<T>& g, const FrameConst& c, int k, T& px, T& py, T& rk) {
+  sample_xy<T, NS>(g, k, px, py);
+  T num, den;
+  depth_ratio<T>(g, c, px, py, num, den);
+  rk = num / den;
+}
+
+// Whether the inverse depth at (px, py) is finite and inside [rho_min,
+// rho_max]. FP64 tests the quotient itself; the float forms test the signs of
+// the differences from the bounds times the denominator (the same test in
+// exact arithmetic, without the division).
+template <typename T>
+__device__ inline bool depth_in_range(const PixelGeom<T>& g, const FrameConst& c, T px, T py, T rmin, T rmax) {
+  T num, den;
+  depth_ratio<T>(g, c, px, py, num, den);
+  if constexpr (sizeof(T) == 8) {
+    const T rk = num / den;
+    return isfinite(rk) & (rk >= rmin) & (rk <= rmax);
+  } else {
+    // rk - rmin and rmax - rk have the signs of (num - rmin den) den and
+    // (rmax den - num) den; each fused difference keeps its exact sign
+    const T lo = fma(-rmin, den, num) * den, hi = fma(rmax, den, -num) * den;
+    return (den != (T)0) & (fmin(lo, hi) >= (T)0);
+  }
 }
 
 // Photometric residual of pattern point j at sample position (px, py).
@@ -233,15 +288,13 @@ __device__ inline T point_residual(const StereoArgs& a, const PixelGeom<T>& g, T
 // Textured pixels lie >= 2 px inside the image, so every point is in bounds.
 template <typename T, typename TI, int PAT>
 __device__ inline T kf_point(const KF_GLOBAL TI* i0, int W, int H, T u, T v, const PixelGeom<T>& g, int j) {
-  T val;
-  if (PAT == KF_PAT_LINE5) {
+  if constexpr (PAT == KF_PAT_LINE5) {
     const T jj = (T)(j - 2);
-    val = bilin_kf<T, TI>(i0, W, H, u + jj * g.l0x, v + jj * g.l0y);
-  } else {
+    return round_to_img<TI, T>(bilin_kf<T, TI>(i0, W, H, u + jj * g.l0x, v + jj * g.l0y));
+  } else {   // a stored element, already in the storage type
     const int iu = (int)u + (j % 5 - 2), iv = (int)v + (j / 5 - 2);
-    val = img_value(i0[(size_t)iv * W + iu]);
+    return img_value(i0[(size_t)iv * W + iu]);
   }
-  return round_to_img<TI, T>(val);
 }
 
 template <typename T>
@@ -298,8 +351,16 @@ __device__ inline bool stereo_pixel(const StereoArgs& a, int idx, bool active, i
 #pragma unroll
     for (int j = 0; j < P; ++j) pat[j] = (G == 64) ? readlane_t(mine, j) : shfl_t(mine, grp * G + j);
   } else {
+    // no branch around the loads, so that all P are in flight together: a
+    // group without a pixel reads the pattern at (2, 2) (in bounds, unused)
+    const T uu = active ? u : (T)2, vv = active ? v : (T)2;
+    if constexpr (PAT == KF_PAT_SQ5X5 && std::is_same<TI, bf16>::value) {
 #pragma unroll
-    for (int j = 0; j < P; ++j) pat[j] = active ? kf_point<T, TI, PAT>(i0, W, H, u, v, g, j) : (T)0;
+      for (int r = 0; r < 5; ++r) row5_bf16(i0, (size_t)((int)vv + r - 2) * W + ((int)uu - 2), &pat[5 * r]);
+    } else {
+#pragma unroll
+      for (int j = 0; j < P; ++j) pat[j] = kf_point<T, TI, PAT>(i0, W, H, uu, vv, g, j);
+    }
   }
 
   // SSD of this lane's samples. LINE5 lanes take S consecutive samples
@@ -307,6 +368,7 @@ __device__ inline bool stereo_pixel(const StereoArgs& a, int idx, bool active, i
   // sample k + 1, so the lane evaluates S + 4 bilinear points instead of 5 S.
   // SQ5X5 lanes take every G-th sample.
   constexpr bool CONSEC = PAT == KF_PAT_LINE5;
+  const T rho_lo = (T)a.fc.rho_min, rho_hi = (T)a.fc.rho_max;
   T ssd[S];
   T best = INF;
   int bestk = 0x7fffffff;
@@ -326,9 +388,9 @@ __device__ inline bool stereo_pixel(const StereoArgs& a, int idx, bool active, i
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     const int k = CONSEC ? gl * S + s : gl + G * s;
-    T px, py, rk;
-    sample_pos<T, NS>(g, a.fc, k, px, py, rk);
-    bool ok = g.ok && isfinite((double)rk) && rk >= (T)a.fc.rho_min && rk <= (T)a.fc.rho_max;
+    T px, py;
+    sample_xy<T, NS>(g, k, px, py);
+    bool ok = g.ok & depth_in_range<T>(g, a.fc, px, py, rho_lo, rho_hi);
     T acc = (T)0;
     if (PAT == KF_PAT_LINE5 && shared_pts) {
 #pragma unroll
@@ -360,6 +422,7 @@ __device__ inline bool stereo_pixel(const StereoArgs& a, int idx, bool active, i
         // 6 x 6 tap window shared by the 25 points (translation-only warp)
         const T fpx = floor(px), fpy = floor(py);
         const T f = px - fpx, gg = py - fpy;
+        const T fm = (T)1 - f, gm = (T)1 - gg;
         const int c0 = (int)fpx - 2, r0 = (int)fpy - 2;
         T hprev[5];
         const KF_GLOBAL uint8_t* base = gp(a.i1s) + (size_t)r0 * st + c0;
@@ -369,13 +432,21 @@ __device__ inline bool stereo_pixel(const StereoArgs& a, int idx, bool active, i
           T t[6];
           taps6<T>(base + (size_t)n * st, t);
           T hrow[5];
+          // FP64 interpolates as a + w (b - a), like the oracle; the float
+          // forms weight both ends, (1 - w) a + w b, which takes one
+          // instruction less per point (the tap difference would be an
+          // integer subtraction and a conversion) and rounds differently
 #pragma unroll
-          for (int m = 0; m < 5; ++m) hrow[m] = t[m] + f * (t[m + 1] - t[m]);
+          for (int m = 0; m < 5; ++m) {
+            if constexpr (sizeof(T) == 8) hrow[m] = t[m] + f * (t[m + 1] - t[m]);
+            else hrow[m] = fma(f, t[m + 1], fm * t[m]);
+          }
           if (n > 0) {
 #pragma unroll
             for (int m = 0; m < 5; ++m) {
-              const T val = hprev[m] + gg * (hrow[m] - hprev[m]);
-              const T e = val - pat[(n - 1) * 5 + m];
+              T e;
+              if constexpr (sizeof(T) == 8) e = hprev[m] + gg * (hrow[m] - hprev[m]) - pat[(n - 1) * 5 + m];
+              else e = fma(gg, hrow[m], fma(gm, hprev[m], -pat[(n - 1) * 5 + m]));
               acc += e * e;
             }
           }
@@ -491,8 +562,10 @@ __global__ __launch_bounds__(ST_THREADS) void k_stereo(StereoArgs a) {
   const int count = gp(a.scal_ro)->mask_count;
   const int groups_per_block = ST_WAVES * GPW;
   const int ngroups = gridDim.x * groups_per_block;
-  const int my_group = blockIdx.x * groups_per_block + wave * GPW + grp;
-  const int rounds = (count + ngroups - 1) / ngroups;
+  const int wave_first = blockIdx.x * groups_per_block + wave * GPW;
+  const int my_group = wave_first + grp;
+  // rounds with at least one pixel for this wavefront (wave-uniform)
+  const int rounds = count > wave_first ? (count - wave_first + ngroups - 1) / ngroups : 0;
   int updated_here = 0;
   for (int r = 0; r < rounds; ++r) {      // wave-uniform trip count (cross-lane operations inside)
     const int idx = my_group + r * ngroups;
@@ -549,7 +622,7 @@ __global__ __launch_bounds__(ST_THREADS) void k_stereo_batch(const StereoArgs* _
   const int total = pref[n];
   const int nwaves = gridDim.x * ST_WAVES;
   const int my_wave = blockIdx.x * ST_WAVES + wave;
-  const int rounds = (total + nwaves - 1) / nwaves;
+  const int rounds = total > my_wave ? (total - my_wave + nwaves - 1) / nwaves : 0;
   for (int r = 0; r < rounds; ++r) {
     const int witem = my_wave + r * nwaves;
     const bool wactive = witem < total;
@@ -601,10 +674,44 @@ __global__ void k_stage_batch(const StereoArgs* __restrict__ tab, const int32_t*
   }
 }
 
+// Workgroups of kernel `k` one compute unit holds at once (its registers and
+// LDS decide), queried once per instantiation; 8 if the query fails.
+template <typename K>
+int resident_per_cu(K k) {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, ST_THREADS, 0) != hipSuccess || n < 1) {
+    (void)hipGetLastError();
+    n = 8;
+  }
+  return n;
+}
+
+// Grid of a stereo launch: beside a running solve (frame pipelining) one
+// workgroup per compute unit, else as many as the device holds at once. The
+// stereo is bound by instruction issue and memory latency, so a single
+// generation of workgroups that stride over the pixel list until it is done
+// beats a grid of several generations, whose last one leaves most SIMDs
+// idle: 640 x 480, SQ5X5, N_s = 128 (3 resident workgroups per compute unit)
+// takes 103 us per frame against 115 us with 6 per unit and 136 us with 8.
+// Beside a solve, whose team waits on its slowest workgroup and so on every
+// SIMD the stereo's waves share, one per unit keeps the stereo hidden and
+// the solve undisturbed (640 x 480 pipelined, 8 / 4 / 2 / 1 / 0.5 per unit:
+// 452 / 464 / 470 / 472 / 465 Mpixel/s; at 0.25 the stereo outlasts the solve).
+template <auto K>
+int stereo_grid(int cus, bool beside_solve) {
+  static const int per_cu = resident_per_cu(K);   // one query per kernel instantiation
+  return beside_solve ? cus : cus * per_cu;
+}
+
 template <typename T, typename TI, int PAT>
-hipError_t stereo_batch_ns(int ns, const StereoArgs* tab, const int32_t* n, int blocks, hipStream_t s) {
+hipError_t stereo_batch_ns(int ns, const StereoArgs* tab, const int32_t* n, int cus, hipStream_t s) {
   switch (ns) {
-#define KF_NS(v) case v: hipLaunchKernelGGL((k_stereo_batch<T, TI, PAT, v>), dim3(blocks), dim3(ST_THREADS), 0, s, tab, n); break;
+#define KF_NS(v)                                                                                        \
+  case v: {                                                                                             \
+    constexpr auto k = k_stereo_batch<T, TI, PAT, v>;                                                   \
+    hipLaunchKernelGGL(k, dim3(stereo_grid<k>(cus, false)), dim3(ST_THREADS), 0, s, tab, n);            \
+    break;                                                                                              \
+  }
     KF_NS(4) KF_NS(8) KF_NS(16) KF_NS(32) KF_NS(64) KF_NS(128) KF_NS(256) KF_NS(512) KF_NS(1024)
 #undef KF_NS
     default: return hipErrorInvalidValue;
@@ -613,17 +720,22 @@ hipError_t stereo_batch_ns(int ns, const StereoArgs* tab, const int32_t* n, int 
 }
 
 template <int PREC>
-hipError_t stereo_batch_prec(int pattern, int ns, const StereoArgs* tab, const int32_t* n, int blocks, hipStream_t s) {
+hipError_t stereo_batch_prec(int pattern, int ns, const StereoArgs* tab, const int32_t* n, int cus, hipStream_t s) {
   using T = typename Form<PREC>::T;
   using TI = typename Form<PREC>::TI;
-  if (pattern == KF_PAT_LINE5) return stereo_batch_ns<T, TI, KF_PAT_LINE5>(ns, tab, n, blocks, s);
-  return stereo_batch_ns<T, TI, KF_PAT_SQ5X5>(ns, tab, n, blocks, s);
+  if (pattern == KF_PAT_LINE5) return stereo_batch_ns<T, TI, KF_PAT_LINE5>(ns, tab, n, cus, s);
+  return stereo_batch_ns<T, TI, KF_PAT_SQ5X5>(ns, tab, n, cus, s);
 }
 
 template <typename T, typename TI, int PAT>
-hipError_t stereo_ns(int ns, const StereoArgs& a, int blocks, hipStream_t s) {
+hipError_t stereo_ns(int ns, const StereoArgs& a, int cus, bool beside_solve, hipStream_t s) {
   switch (ns) {
-#define KF_NS(n) case n: hipLaunchKernelGGL((k_stereo<T, TI, PAT, n>), dim3(blocks), dim3(ST_THREADS), 0, s, a); break;
+#define KF_NS(v)                                                                                        \
+  case v: {                                                                                             \
+    constexpr auto k = k_stereo<T, TI, PAT, v>;                                                         \
+    hipLaunchKernelGGL(k, dim3(stereo_grid<k>(cus, beside_solve)), dim3(ST_THREADS), 0, s, a);          \
+    break;                                                                                              \
+  }
     KF_NS(4) KF_NS(8) KF_NS(16) KF_NS(32) KF_NS(64) KF_NS(128) KF_NS(256) KF_NS(512) KF_NS(1024)
 #undef KF_NS
     default: return hipErrorInvalidValue;
@@ -632,39 +744,37 @@ hipError_t stereo_ns(int ns, const StereoArgs& a, int blocks, hipStream_t s) {
 }
 
 template <int PREC>
-hipError_t stereo_prec(int pattern, int ns, const StereoArgs& a, int blocks, hipStream_t s) {
+hipError_t stereo_prec(int pattern, int ns, const StereoArgs& a, int cus, bool beside_solve, hipStream_t s) {
   using T = typename Form<PREC>::T;
   using TI = typename Form<PREC>::TI;
-  if (pattern == KF_PAT_LINE5) return stereo_ns<T, TI, KF_PAT_LINE5>(ns, a, blocks, s);
-  return stereo_ns<T, TI, KF_PAT_SQ5X5>(ns, a, blocks, s);
+  if (pattern == KF_PAT_LINE5) return stereo_ns<T, TI, KF_PAT_LINE5>(ns, a, cus, beside_solve, s);
+  return stereo_ns<T, TI, KF_PAT_SQ5X5>(ns, a, cus, beside_solve, s);
 }
 
 }  // namespace
 
-int stereo_grid_blocks(int device, bool beside_solve) {
+int device_cus(int device) {
   int cus = 256;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) cus = 256;
-  // Beside a running solve (frame pipelining), one workgroup per compute unit:
-  // the stereo takes longer but stays hidden under the solve, whose team waits
-  // on its slowest workgroup and so on every SIMD the stereo's waves share.
-  // 640 x 480 headline: 8 / 4 / 2 / 1 / 0.5 workgroups per compute unit give
-  // 452 / 464 / 470 / 472 / 465 Mpixel/s (0.25: 330, the stereo then outlasts
-  // the solve).
-  return beside_solve ? cus : cus * 8;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1) {
+    (void)hipGetLastError();
+    cus = 256;
+  }
+  return cus;
 }
 
 hipError_t launch_stereo_batch(int prec, int pattern, int ns, const StereoArgs* tab, const int32_t* n, int nmax,
-                               int blocks, hipStream_t s) {
+                               int cus, hipStream_t s) {
   hipLaunchKernelGGL(k_stage_batch, dim3(64, nmax), dim3(256), 0, s, tab, n);
   switch (prec) {
-    case KF_F64: return stereo_batch_prec<KF_F64>(pattern, ns, tab, n, blocks, s);
-    case KF_F32: return stereo_batch_prec<KF_F32>(pattern, ns, tab, n, blocks, s);
-    case KF_BF16_F32: return stereo_batch_prec<KF_BF16_F32>(pattern, ns, tab, n, blocks, s);
+    case KF_F64: return stereo_batch_prec<KF_F64>(pattern, ns, tab, n, cus, s);
+    case KF_F32: return stereo_batch_prec<KF_F32>(pattern, ns, tab, n, cus, s);
+    case KF_BF16_F32: return stereo_batch_prec<KF_BF16_F32>(pattern, ns, tab, n, cus, s);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_stereo(int prec, int pattern, int ns, const StereoArgs& a, int blocks, hipStream_t s) {
+hipError_t launch_stereo(int prec, int pattern, int ns, const StereoArgs& a, int cus, bool beside_solve,
+                         hipStream_t s) {
   hipLaunchKernelGGL(k_frame_begin, dim3(1), dim3(1), 0, s, a.scal, a.buf, a.fc.trans);
   {
     const int total = (a.H + 1) * a.i1_stride;
@@ -673,9 +783,9 @@ hipError_t launch_stereo(int prec, int pattern, int ns, const StereoArgs& a, int
     hipLaunchKernelGGL(k_stage_frame, dim3(nb), dim3(256), 0, s, a.i1, a.i1s, a.W, a.H, a.i1_stride);
   }
   switch (prec) {
-    case KF_F64: return stereo_prec<KF_F64>(pattern, ns, a, blocks, s);
-    case KF_F32: return stereo_prec<KF_F32>(pattern, ns, a, blocks, s);
-    case KF_BF16_F32: return stereo_prec<KF_BF16_F32>(pattern, ns, a, blocks, s);
+    case KF_F64: return stereo_prec<KF_F64>(pattern, ns, a, cus, beside_solve, s);
+    case KF_F32: return stereo_prec<KF_F32>(pattern, ns, a, cus, beside_solve, s);
+    case KF_BF16_F32: return stereo_prec<KF_BF16_F32>(pattern, ns, a, cus, beside_solve, s);
   }
   return hipErrorInvalidValue;
 }
