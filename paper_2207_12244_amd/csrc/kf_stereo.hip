@@ -26,10 +26,12 @@ constexpr int ST_WAVES = ST_THREADS / 64;
 // sub-pixel step, filter, and for the 25-point patch below 25 lanes the
 // keyframe pattern itself) is repeated by every lane of the group, so smaller
 // groups do less of it per pixel; 16 samples per lane is where the lane's own
-// sample registers still fit. Measured per 640 x 480 frame: SQ5X5 at N_s =
-// 32 / 64 / 128 takes 63 / 93 / 138 us (f32) with 2 / 4 / 8 lanes, against
-// 134 / 141 / 156 us with 32 lanes and 229 us with 4 lanes at N_s = 128; LINE5
-// at N_s = 32 and 64 is slower with half or twice its group. The argmin is a
+// sample registers still fit. Measured per 640 x 480 frame with a grid of 8
+// workgroups per compute unit: SQ5X5 at N_s = 32 / 64 / 128 takes 63 / 93 /
+// 138 us (f32) with 2 / 4 / 8 lanes, against 134 / 141 / 156 us with 32 lanes
+// and 229 us with 4 lanes at N_s = 128; LINE5 at N_s = 32 and 64 is slower
+// with half or twice its group. With the resident grid (bf16 form, N_s =
+// 128): 103 us with 8 lanes, 120 / 118 us with 16 / 4. The argmin is a
 // lexicographic (SSD, k) minimum, so the split only changes which lane
 // evaluates a sample.
 constexpr int lanes_per_pixel(int, int ns) {
