@@ -111,21 +111,36 @@ double team_cost(const kf_ctx* c) {
   return g.n_gn * (cg + 2.0) * iteration_us(c->tiling);
 }
 
-// List schedule of the active teams over the `grid` workgroups: teams in
-// order of decreasing cost, each on the workgroups that become free first
-// (ties to the lower workgroup index, which spreads a team evenly over the
-// XCDs because consecutive workgroups of a launch are dispatched to
-// consecutive XCDs). Every workgroup's queue follows the one global team
-// order, which keeps the launch free of deadlock.
+// List schedule of the active teams over the `grid` workgroups. A team runs
+// on the B workgroups that become free first (ties to the lower workgroup
+// index, which spreads a team evenly over the XCDs because consecutive
+// workgroups of a launch are dispatched to consecutive XCDs) and starts when
+// the last of them is free. The next team placed is the one that can start
+// earliest (ties: the most work, cost x B, then the lower member index), so
+// small teams fill the workgroups that larger ones would leave waiting: on the
+// 64-keyframe mix the estimated makespan drops from 1.17 to 1.04 times the
+// busy-time bound of the decreasing-cost order. Every workgroup's queue
+// follows the one global team order, which keeps the launch free of deadlock.
 void schedule(kf_batch* b, const std::vector<int>& active) {
-  std::vector<int> order(active);
   std::vector<double> cost(b->m.size(), 0.0);
-  for (int c : order) cost[c] = team_cost(b->m[c]);
-  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+  for (int c : active) cost[c] = team_cost(b->m[c]);
   std::vector<double> avail(b->grid, 0.0);
   std::vector<std::vector<int32_t>> q(b->grid);
   std::vector<int> idx(b->grid);
-  for (int c : order) {
+  std::vector<double> sorted_avail(b->grid);
+  std::vector<int> rest(active);
+  while (!rest.empty()) {
+    sorted_avail = avail;
+    std::sort(sorted_avail.begin(), sorted_avail.end());
+    size_t pick = 0;
+    for (size_t r = 1; r < rest.size(); ++r) {
+      const int x = rest[r], y = rest[pick];
+      const double sx = sorted_avail[b->m[x]->tiling.blocks - 1], sy = sorted_avail[b->m[y]->tiling.blocks - 1];
+      const double wx = cost[x] * b->m[x]->tiling.blocks, wy = cost[y] * b->m[y]->tiling.blocks;
+      if (sx < sy || (sx == sy && (wx > wy || (wx == wy && x < y)))) pick = r;
+    }
+    const int c = rest[pick];
+    rest.erase(rest.begin() + (std::ptrdiff_t)pick);
     const int B = b->m[c]->tiling.blocks;
     for (int g = 0; g < b->grid; ++g) idx[g] = g;
     std::partial_sort(idx.begin(), idx.begin() + B, idx.end(), [&](int x, int y) {
