@@ -636,7 +636,8 @@ kf_status kf_stereo_update(kf_ctx* c, const uint8_t* image1, const double T_wc1[
     if (c->solve_pending[nxt]) e = hipStreamWaitEvent(c->stream, c->ev_solve[nxt], 0);
   }
   // beside a solve still in flight the update takes one workgroup per compute
-  // unit; with none in flight (the user stream waited for them all) the full grid
+  // unit; with none in flight (the user stream waited for them all) the
+  // resident grid
   const bool beside = c->cfg.pipeline_frames && !c->solves_waited;
   if (e == hipSuccess) e = launch_stereo(c->cfg.precision, c->cfg.pattern, c->cfg.n_samples, a, c->cus, beside, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "kf_stereo_update");

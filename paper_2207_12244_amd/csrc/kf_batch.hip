@@ -117,10 +117,11 @@ double team_cost(const kf_ctx* c) {
 // workgroups of a launch are dispatched to consecutive XCDs) and starts when
 // the last of them is free. The next team placed is the one that can start
 // earliest (ties: the most work, cost x B, then the lower member index), so
-// small teams fill the workgroups that larger ones would leave waiting: on the
-// 64-keyframe mix the estimated makespan drops from 1.17 to 1.04 times the
-// busy-time bound of the decreasing-cost order. Every workgroup's queue
-// follows the one global team order, which keeps the launch free of deadlock.
+// small teams fill the workgroups that larger ones would leave waiting. On the
+// 64-keyframe mix the cost model's makespan is 1.04 times its busy-time bound,
+// against 1.17 with the teams placed in order of decreasing cost (measured:
+// 7.4 against 8.3 ms per batched solve). Every workgroup's queue follows the
+// one global team order, which keeps the launch free of deadlock.
 void schedule(kf_batch* b, const std::vector<int>& active) {
   std::vector<double> cost(b->m.size(), 0.0);
   for (int c : active) cost[c] = team_cost(b->m[c]);
