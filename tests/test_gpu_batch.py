@@ -111,3 +111,34 @@ def test_batch_subset_calls_equal_solo():
     for i in range(len(cases)):
         _assert_same(_state(solo[i]), _state(members[i]), f"member {i}")
     batch.close()
+
+
+def test_batch_schedule_fills_the_workgroups():
+    """The batched workload's 64-keyframe mix at 512 threads x 10 px per thread
+    (14 x 160x120, 22 x 320x240, 16 x 512x384, 12 x 640x480: 4 / 15 / 39 / 60
+    tiles) puts 1,730 team members on 256 workgroups. The host places next the
+    team that can start earliest, so small teams fill the workgroups that large
+    ones would leave waiting, and the longest queue holds ceil(1730 / 256) = 7
+    teams (placing the teams in order of decreasing cost left gaps: 8)."""
+    from paper_2207_12244_amd.autotune import tiles_for
+    from paper_2207_12244_amd.kf import Batch, Keyframe
+    t = torch()
+    if t.cuda.get_device_properties(0).multi_processor_count != 256:
+        pytest.skip("the expected queue length is for a 256-CU device")
+    mix = {(160, 120): 14, (320, 240): 22, (512, 384): 16, (640, 480): 12}
+    members, total = [], 0
+    for (W, H), n in mix.items():
+        tx, ty = tiles_for(W, H, 512, 10)
+        K = np.array([[0.8 * W, 0.0, W / 2.0], [0.0, 0.8 * W, H / 2.0], [0.0, 0.0, 1.0]])
+        for _ in range(n):
+            members.append(Keyframe(W, H, K=K, tiles=(tx, ty), **BATCH_KW))
+        total += n * tx * ty
+    batch = Batch(members, use_graph=False)
+    lay = batch.layout()
+    say(f"schedule of the 64-keyframe mix: {total} team members, layout {lay}")
+    assert total == 1730
+    assert lay["workgroups"] == 256 and lay["ppt"] == 10, lay
+    assert lay["max_queue"] == -(-total // 256), lay
+    batch.close()
+    for m in members:
+        m.close()
